@@ -1,0 +1,108 @@
+"""Micromagnetic exchange, LLG right-hand side and RK4 in FP64 (oracle; test
+infrastructure only).
+
+* Exchange field, Eq. (4) (Sec. III): H_ex = 2A/(mu0 Ms) * lap(m), with the
+  7-point Laplacian sum_d (m[i+e_d] - 2 m[i] + m[i-e_d]) / h_d^2.  The paper
+  states no boundary condition; free (Neumann) boundaries are taken: a missing
+  neighbour is replaced by m[i] itself, so it contributes nothing.  An axis with a
+  single cell contributes no term.
+* LLG, Eq. (5), rewritten in explicit Landau-Lifshitz form:
+      dm/dt = -gamma/(1+alpha^2) * [m x H + alpha m x (m x H)].
+* Effective field (Sec. III): H_eff = H_d + H_ex + H_Zee (constant Zeeman).
+* RK4 (Sec. III): the classic four-stage scheme; H_d is recomputed at every
+  stage; m is renormalised to unit length once, at the end of each step.
+
+gamma is a parameter; its default is mu0 * gamma_e = 2.21276e5 m/(A s)
+(the paper gives no value).
+"""
+
+import numpy as np
+
+from . import demag
+
+MU0 = 4e-7 * np.pi
+GAMMA = 2.21276e5  # mu0 * 1.76086e11, m/(A s)
+
+
+def exchange_field(m, cell, A, Ms):
+    """H_ex = 2A/(mu0 Ms) lap(m) with free boundaries; m is (3, nz, ny, nx)."""
+    m = np.asarray(m, dtype=np.float64)
+    dx, dy, dz = cell
+    lap = np.zeros_like(m)
+    for axis, h in ((3, dx), (2, dy), (1, dz)):
+        n = m.shape[axis]
+        if n == 1:
+            continue
+        fwd = np.zeros_like(m)  # m[i+1] - m[i], zero at the last cell
+        bwd = np.zeros_like(m)  # m[i-1] - m[i], zero at the first cell
+        sl_lo = [slice(None)] * 4
+        sl_hi = [slice(None)] * 4
+        sl_lo[axis] = slice(0, n - 1)
+        sl_hi[axis] = slice(1, n)
+        sl_lo, sl_hi = tuple(sl_lo), tuple(sl_hi)
+        fwd[sl_lo] = m[sl_hi] - m[sl_lo]
+        bwd[sl_hi] = m[sl_lo] - m[sl_hi]
+        lap += (fwd + bwd) / (h * h)
+    return 2.0 * A / (MU0 * Ms) * lap
+
+
+def llg_rhs(m, H, alpha, gamma=GAMMA):
+    """Landau-Lifshitz form of Eq. (5); m and H are (3, ...) arrays."""
+    mxH = np.cross(m, H, axis=0)
+    mxmxH = np.cross(m, mxH, axis=0)
+    return -gamma / (1.0 + alpha * alpha) * (mxH + alpha * mxmxH)
+
+
+class LLG:
+    """Thin-film LLG problem: mesh n = (nx, ny, nz), cell (dx, dy, dz) in m."""
+
+    def __init__(self, n, cell, Ms, A, alpha, gamma=GAMMA, Hzee=(0.0, 0.0, 0.0),
+                 workers=None, demag_on=True):
+        self.n = tuple(int(v) for v in n)
+        self.cell = tuple(float(c) for c in cell)
+        self.Ms, self.A, self.alpha, self.gamma = float(Ms), float(A), float(alpha), float(gamma)
+        self.Hzee = np.asarray(Hzee, dtype=np.float64).reshape(3, 1, 1, 1)
+        self.demag = demag.DemagFFT(self.n, self.cell, workers) if demag_on else None
+
+    def field(self, m):
+        H = exchange_field(m, self.cell, self.A, self.Ms) + self.Hzee
+        if self.demag is not None:
+            H = H + self.demag(self.Ms * m)
+        return H
+
+    def rhs(self, m):
+        return llg_rhs(m, self.field(m), self.alpha, self.gamma)
+
+    def rk4_step(self, m, dt):
+        m = np.asarray(m, dtype=np.float64)
+        k1 = self.rhs(m)
+        k2 = self.rhs(m + 0.5 * dt * k1)
+        k3 = self.rhs(m + 0.5 * dt * k2)
+        k4 = self.rhs(m + dt * k3)
+        out = m + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+        return out / np.linalg.norm(out, axis=0, keepdims=True)
+
+    def run(self, m, dt, nsteps):
+        for _ in range(nsteps):
+            m = self.rk4_step(m, dt)
+        return m
+
+    def energy(self, m):
+        """Exchange + demag + Zeeman energy (J) of the discrete system:
+        E = -mu0 Ms V sum_i m_i . (H_ex/2 + H_d/2 + H_zee)."""
+        V = float(np.prod(self.cell))
+        Hhalf = 0.5 * exchange_field(m, self.cell, self.A, self.Ms)
+        if self.demag is not None:
+            Hhalf = Hhalf + 0.5 * self.demag(self.Ms * m)
+        Hhalf = Hhalf + self.Hzee
+        return float(-MU0 * self.Ms * V * np.sum(m * Hhalf))
+
+
+def macrospin_closed_form(theta0, phi0, H, alpha, t, gamma=GAMMA):
+    """Single moment in a constant field H along +z (LL form):
+    tan(theta/2) = tan(theta0/2) exp(-alpha gamma H t/(1+alpha^2)),
+    phi = phi0 + gamma H t/(1+alpha^2).  Returns the unit vector (3,)."""
+    g = gamma * H / (1.0 + alpha * alpha)
+    theta = 2.0 * np.arctan(np.tan(theta0 / 2.0) * np.exp(-alpha * g * t))
+    phi = phi0 + g * t
+    return np.array([np.sin(theta) * np.cos(phi), np.sin(theta) * np.sin(phi), np.cos(theta)])
