@@ -1,0 +1,188 @@
+/*
+ * demag.h -- C ABI of the MI355X (gfx950) demagnetizing-field engine.
+ *
+ * The library evaluates the demagnetizing field of Eq. (1) (Sec. II),
+ *     H_d,i = - sum_j N(i - j) . M_j      (sum over every mesh cell, j = i included),
+ * on a single GPU as a zero-padded 3-D FFT convolution (Sec. II, Fig. 1, App. A),
+ * and advances the LLG equation (Eq. 5, Sec. III) and the atomistic stochastic
+ * LLG equation at T = 0 (Eq. 10, Sec. IV) with it.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Field arrays (M, H, m, S) are caller-owned DEVICE pointers to contiguous
+ *    FP32 data laid out structure-of-arrays as [3][nz][ny][nx] (component, z, y,
+ *    x; x fastest).  Nothing is copied; the library never frees them.
+ *  - Units are SI: M and H in A/m, lengths in m, gamma in m/(A s), J in J.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call except
+ *    the *_setup / *_destroy calls only enqueues work on that stream and returns;
+ *    the caller synchronises.  Plans own their device workspace, so one plan must
+ *    not be used by two streams at the same time.
+ *  - Every call returns a status code (DEMAG_OK = 0 or a negative DEMAG_E*).
+ *    No exception, exit or abort crosses the ABI.  demag_last_error() returns a
+ *    thread-local, human-readable message describing the last failure on the
+ *    calling thread.  A failed call leaves its outputs unspecified but the plan
+ *    usable unless the status is DEMAG_EHIP (a HIP runtime failure).
+ *  - Mesh sizes: every n_d must be 1 or a power of two, n_x and n_y at most 2048
+ *    and n_z at most 128 (larger or other sizes return DEMAG_EUNSUPPORTED).
+ *    The padded transform length is N_d = 2 n_d, or 1 when n_d = 1.
+ */
+#ifndef DEMAG_H
+#define DEMAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+    DEMAG_OK = 0,
+    DEMAG_EINVAL = -1,        /* bad argument (null pointer, size <= 0, non-finite cell) */
+    DEMAG_ENOMEM = -2,        /* device allocation failed or budget exceeded */
+    DEMAG_EUNSUPPORTED = -3,  /* mesh size the kernels do not implement */
+    DEMAG_EHIP = -4,          /* a HIP runtime call failed */
+    DEMAG_EBUSY = -5          /* serving: request not finished / queue full */
+};
+
+/* ---- plan flags --------------------------------------------------------- */
+enum {
+    DEMAG_FP32 = 0            /* FP32 FFT stages (default) */
+};
+
+/* Mesh of n_x x n_y x n_z rectangular cells of size dx x dy x dz (m). */
+typedef struct {
+    int32_t nx, ny, nz;
+    double dx, dy, dz;
+} demag_mesh;
+
+typedef struct demag_plan demag_plan;   /* opaque; owns N^ and the FFT workspace */
+
+/*
+ * demag_setup -- build a plan for one mesh: computes the transformed
+ * demagnetizing tensor N^ (the "convolution kernel" of App. A, computed at
+ * initialisation as in Sec. II) in FP64 on the GPU, stores its six independent
+ * real components in FP32 packed by the y and z symmetries, and allocates the
+ * FFT workspace.
+ *   mesh    in   mesh description (copied).
+ *   flags   in   DEMAG_FP32.
+ *   stream  in   hipStream_t used for the set-up kernels; the call synchronises it.
+ *   out     out  receives the new plan (NULL on failure).
+ * Errors: EINVAL (null/invalid mesh), EUNSUPPORTED (size), ENOMEM, EHIP.
+ */
+int demag_setup(const demag_mesh* mesh, uint32_t flags, void* stream, demag_plan** out);
+
+/*
+ * demag_field -- H = H_d(M) of Eq. (1): x R2C -> y FFT -> (z FFT, N^.M^, z IFFT)
+ * -> y IFFT -> x C2R (App. A execution order, without the inter-GPU transfers).
+ *   M  in   device, FP32 [3][nz][ny][nx], A/m.
+ *   H  out  device, FP32 [3][nz][ny][nx], A/m; must not alias M.
+ * Errors: EINVAL (null plan/pointer, H == M), EHIP.
+ */
+int demag_field(demag_plan* plan, const float* M, float* H, void* stream);
+
+/* Bytes of device memory a plan for `mesh` holds (N^ + FFT workspace), for
+ * budget-based admission. Returns 0 for an invalid or unsupported mesh. */
+size_t demag_plan_bytes(const demag_mesh* mesh, uint32_t flags);
+
+/*
+ * demag_get_kernel -- copy the packed FP32 transformed tensor into `dst`
+ * (device), laid out [6][Z1][X1][Y1] with components (xx, yy, zz, xy, xz, yz)
+ * and D1 = N_d/2 + 1 (1 when N_d = 1).  The stored value already includes the
+ * factor -1/(N_x N_y N_z) of Eq. (1) and the unnormalised inverse transforms.
+ * `count` is the capacity of dst in floats; returns EINVAL if too small.
+ */
+int demag_get_kernel(demag_plan* plan, float* dst, size_t count, void* stream);
+
+int demag_destroy(demag_plan* plan);
+
+/* ---- micromagnetic LLG (Eqs. 4, 5; RK4 of Sec. III) --------------------- */
+typedef struct {
+    double Ms;        /* saturation magnetisation, A/m (> 0) */
+    double A;         /* exchange stiffness, J/m (Eq. 4) */
+    double alpha;     /* Gilbert damping (>= 0) */
+    double gamma;     /* gyromagnetic ratio, m/(A s) (> 0) */
+    double Hzee[3];   /* constant applied field, A/m */
+} llg_params;
+
+/*
+ * llg_step -- advance the unit magnetisation m by `nsteps` classic RK4 steps of
+ * the LLG equation in Landau-Lifshitz form,
+ *     dm/dt = -gamma/(1+alpha^2) [m x H_eff + alpha m x (m x H_eff)],
+ * with H_eff = H_d(Ms m) + 2A/(mu0 Ms) lap(m) + Hzee (free boundaries; Eq. 4),
+ * H_d recomputed at every RK stage, and |m| renormalised at the end of each step.
+ *   m       in/out device FP32 [3][nz][ny][nx], unit vectors, updated in place.
+ * Errors: EINVAL (null, nsteps < 0, dt not finite, bad params), ENOMEM, EHIP.
+ */
+int llg_step(demag_plan* plan, float* m, const llg_params* params, double dt,
+             int32_t nsteps, void* stream);
+
+/* ---- atomistic spin dynamics (Eqs. 7, 9, 10; Sec. IV) ------------------- */
+typedef struct {
+    int32_t nx, ny, nz;   /* spins on a simple-cubic lattice */
+    double a;             /* lattice constant, m */
+    int32_t macro;        /* macrocell edge in spins (N_S = macro^3); must divide n_d */
+} atom_mesh;
+
+typedef struct {
+    double J;             /* nearest-neighbour exchange energy, J (Eq. 7) */
+    double mu_s;          /* spin moment in Bohr magnetons */
+    double alpha, gamma;
+    double Hzee[3];
+} atom_params;
+
+typedef struct atom_plan atom_plan;   /* owns a demag_plan on the macrocell mesh */
+
+/* atom_setup -- plan for a lattice; the demagnetizing field is evaluated on the
+ * spin-averaged macrocell mesh (Eq. 9) of edge h = macro * a. */
+int atom_setup(const atom_mesh* mesh, uint32_t flags, void* stream, atom_plan** out);
+
+/*
+ * atom_step -- `nsteps` Heun steps of Eq. (10) at T = 0 for the unit spins S:
+ * H = J/(mu0 mu_B mu_s) sum_nn S_j (Eq. 7, open boundaries)
+ *   + H_d of the spin's macrocell (Eq. 9 then Eq. 1) + Hzee;
+ * predictor S + dt f(S), corrector S + dt/2 (f(S) + f(S_p)), renormalised at
+ * the end of each step.
+ *   S  in/out device FP32 [3][nz][ny][nx] unit vectors, updated in place.
+ */
+int atom_step(atom_plan* plan, float* S, const atom_params* params, double dt,
+              int32_t nsteps, void* stream);
+
+int atom_destroy(atom_plan* plan);
+
+/* ---- per-stage timing (tracing) ----------------------------------------- */
+/* Kernel stages a plan launches, in pipeline order. */
+enum {
+    DEMAG_STAGE_X_FWD = 0,    /* x R2C (+ transposed store) */
+    DEMAG_STAGE_Y_FWD = 1,    /* y FFT */
+    DEMAG_STAGE_Z_CONV = 2,   /* z FFT, N^.M^, z IFFT */
+    DEMAG_STAGE_Y_INV = 3,    /* y IFFT */
+    DEMAG_STAGE_X_INV = 4,    /* x C2R */
+    DEMAG_STAGE_LLG = 5,      /* exchange + LLG RK4 stage update */
+    DEMAG_NSTAGES = 6
+};
+
+/*
+ * demag_timing_enable -- when max_records > 0, every later stage launch of this
+ * plan is bracketed by a pair of HIP events on its stream (up to max_records
+ * launches per stage; further launches are not timed).  0 disables timing and
+ * frees the events.  Timing adds two event records per launch.
+ */
+int demag_timing_enable(demag_plan* plan, int32_t max_records);
+
+/*
+ * demag_timing_read -- waits for the recorded events, writes the summed elapsed
+ * time (ms) and the number of timed launches of each stage into
+ * total_ms[DEMAG_NSTAGES] and launches[DEMAG_NSTAGES], and clears the records.
+ */
+int demag_timing_read(demag_plan* plan, double* total_ms, int32_t* launches);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* demag_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEMAG_H */

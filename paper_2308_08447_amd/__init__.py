@@ -1,0 +1,200 @@
+"""MI355X (gfx950) demagnetizing-field engine: Python binding of the C ABI.
+
+Every function here only marshals arguments to the shared library
+``libdemag.so`` built from ``csrc/`` (see ``include/demag.h``); every step of the
+computation runs in the library's HIP kernels.  There is no fallback: if the
+library is missing or cannot be loaded, ``load()`` raises.
+
+Device arrays are passed as raw pointers; with PyTorch use ``t.data_ptr()`` and
+``torch.cuda.current_stream().cuda_stream`` for the stream.
+"""
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdemag.so")
+
+DEMAG_OK = 0
+DEMAG_EINVAL = -1
+DEMAG_ENOMEM = -2
+DEMAG_EUNSUPPORTED = -3
+DEMAG_EHIP = -4
+DEMAG_EBUSY = -5
+DEMAG_FP32 = 0
+
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EUNSUPPORTED", -4: "EHIP", -5: "EBUSY"}
+
+# symbols declared in include/demag.h
+EXPORTS = (
+    "demag_setup", "demag_field", "demag_plan_bytes", "demag_get_kernel", "demag_destroy",
+    "llg_step", "atom_setup", "atom_step", "atom_destroy", "demag_timing_enable",
+    "demag_timing_read", "demag_last_error",
+)
+STAGES = ("x_fwd", "y_fwd", "z_conv", "y_inv", "x_inv", "llg")
+
+
+class demag_mesh(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double)]
+
+
+class llg_params(ctypes.Structure):
+    _fields_ = [("Ms", ctypes.c_double), ("A", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("Hzee", ctypes.c_double * 3)]
+
+
+class atom_mesh(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("a", ctypes.c_double), ("macro", ctypes.c_int32)]
+
+
+class atom_params(ctypes.Structure):
+    _fields_ = [("J", ctypes.c_double), ("mu_s", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("Hzee", ctypes.c_double * 3)]
+
+
+class DemagError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path=None):
+    """Load the HIP library (once).  Raises if it is missing: there is no fallback."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"HIP library not built: {p} (run python -m paper_2308_08447_amd.build)")
+    lib = ctypes.CDLL(p)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "demag_setup": ([P(demag_mesh), ctypes.c_uint32, vp, P(vp)], ctypes.c_int),
+        "demag_field": ([vp, vp, vp, vp], ctypes.c_int),
+        "demag_plan_bytes": ([P(demag_mesh), ctypes.c_uint32], sz),
+        "demag_get_kernel": ([vp, vp, sz, vp], ctypes.c_int),
+        "demag_destroy": ([vp], ctypes.c_int),
+        "llg_step": ([vp, vp, P(llg_params), ctypes.c_double, ctypes.c_int32, vp], ctypes.c_int),
+        "atom_setup": ([P(atom_mesh), ctypes.c_uint32, vp, P(vp)], ctypes.c_int),
+        "atom_step": ([vp, vp, P(atom_params), ctypes.c_double, ctypes.c_int32, vp], ctypes.c_int),
+        "atom_destroy": ([vp], ctypes.c_int),
+        "demag_timing_enable": ([vp, ctypes.c_int32], ctypes.c_int),
+        "demag_timing_read": ([vp, P(ctypes.c_double), P(ctypes.c_int32)], ctypes.c_int),
+        "demag_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def last_error():
+    return load().demag_last_error().decode()
+
+
+def _check(status):
+    if status != DEMAG_OK:
+        raise DemagError(status, last_error())
+    return status
+
+
+def _ptr(x):
+    """Device pointer of a torch tensor (or an int address / None)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---------------------------------------------------------------- C-ABI mirrors
+def demag_setup(mesh, flags=DEMAG_FP32, stream=None):
+    """mesh = (nx, ny, nz, dx, dy, dz) or a demag_mesh; returns an opaque plan handle."""
+    if not isinstance(mesh, demag_mesh):
+        mesh = demag_mesh(*mesh)
+    out = ctypes.c_void_p()
+    _check(load().demag_setup(ctypes.byref(mesh), flags, _stream(stream), ctypes.byref(out)))
+    return out.value
+
+
+def demag_field(plan, M, H, stream=None):
+    return _check(load().demag_field(plan, _ptr(M), _ptr(H), _stream(stream)))
+
+
+def demag_plan_bytes(mesh, flags=DEMAG_FP32):
+    if not isinstance(mesh, demag_mesh):
+        mesh = demag_mesh(*mesh)
+    return load().demag_plan_bytes(ctypes.byref(mesh), flags)
+
+
+def demag_get_kernel(plan, dst, count, stream=None):
+    return _check(load().demag_get_kernel(plan, _ptr(dst), count, _stream(stream)))
+
+
+def demag_destroy(plan):
+    return _check(load().demag_destroy(plan))
+
+
+def llg_step(plan, m, params, dt, nsteps, stream=None):
+    """params = (Ms, A, alpha, gamma, (Hx, Hy, Hz)) or an llg_params."""
+    if not isinstance(params, llg_params):
+        Ms, A, alpha, gamma, hz = params
+        params = llg_params(Ms, A, alpha, gamma, (ctypes.c_double * 3)(*hz))
+    return _check(load().llg_step(plan, _ptr(m), ctypes.byref(params), dt, nsteps, _stream(stream)))
+
+
+def demag_timing_enable(plan, max_records):
+    return _check(load().demag_timing_enable(plan, max_records))
+
+
+def demag_timing_read(plan):
+    """{stage name: (total_ms, launches)} since the last read."""
+    n = len(STAGES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int32 * n)()
+    _check(load().demag_timing_read(plan, ms, cnt))
+    return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+
+def atom_setup(mesh, flags=DEMAG_FP32, stream=None):
+    """mesh = (nx, ny, nz, a, macro) or an atom_mesh."""
+    if not isinstance(mesh, atom_mesh):
+        mesh = atom_mesh(*mesh)
+    out = ctypes.c_void_p()
+    _check(load().atom_setup(ctypes.byref(mesh), flags, _stream(stream), ctypes.byref(out)))
+    return out.value
+
+
+def atom_step(plan, S, params, dt, nsteps, stream=None):
+    """params = (J, mu_s, alpha, gamma, (Hx, Hy, Hz)) or an atom_params."""
+    if not isinstance(params, atom_params):
+        J, mu_s, alpha, gamma, hz = params
+        params = atom_params(J, mu_s, alpha, gamma, (ctypes.c_double * 3)(*hz))
+    return _check(load().atom_step(plan, _ptr(S), ctypes.byref(params), dt, nsteps, _stream(stream)))
+
+
+def atom_destroy(plan):
+    return _check(load().atom_destroy(plan))
+
+
+def kernel_shape(n):
+    """(6, Z1, X1, Y1) of the packed kernel for a mesh n = (nx, ny, nz)."""
+    d = [1 if v == 1 else v + 1 for v in n]
+    return (6, d[2], d[0], d[1])

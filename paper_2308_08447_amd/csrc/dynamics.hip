@@ -1,0 +1,223 @@
+// dynamics.hip -- exchange + LLG RK4 stage update (Eqs. 4, 5; Sec. III) and the
+// atomistic Heun step (Eqs. 7, 9, 10; Sec. IV) on gfx950.
+//
+// All kernels stream [3][nz][ny][nx] FP32 fields, one thread per cell, x fastest
+// so that every component load is a coalesced row; neighbours along x come from
+// the same or adjacent cache lines and neighbours along y/z from rows the
+// neighbouring wavefronts also read (L1/L2 hits).
+#include "engine.h"
+
+namespace dm {
+
+namespace {
+
+__device__ __forceinline__ float3 cross3(float3 a, float3 b) {
+    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+
+// Landau-Lifshitz right-hand side: -gam [m x H + alpha m x (m x H)]
+__device__ __forceinline__ float3 ll_rhs(float3 m, float3 H, float gam, float alpha) {
+    float3 mxH = cross3(m, H);
+    float3 mmH = cross3(m, mxH);
+    return make_float3(-gam * (mxH.x + alpha * mmH.x), -gam * (mxH.y + alpha * mmH.y),
+                       -gam * (mxH.z + alpha * mmH.z));
+}
+
+__device__ __forceinline__ float3 load3(const float* __restrict__ f, size_t i, size_t N) {
+    return make_float3(f[i], f[i + N], f[i + 2 * N]);
+}
+__device__ __forceinline__ void store3(float* __restrict__ f, size_t i, size_t N, float3 v) {
+    f[i] = v.x;
+    f[i + N] = v.y;
+    f[i + 2 * N] = v.z;
+}
+
+// ---------------------------------------------------------------- micromagnetic
+// Stage s of classic RK4 on m (step start) with stage input ms:
+//   k_s = LL(ms, H_d + H_ex(ms) + H_zee)
+//   s=0: acc = k1,      out = m + dt/2 k1
+//   s=1: acc += 2 k2,   out = m + dt/2 k2
+//   s=2: acc += 2 k3,   out = m + dt k3
+//   s=3: out = normalise(m + dt/6 (acc + k4))   (out may alias m)
+__global__ __launch_bounds__(256) void llg_stage_kernel(LLGStageArgs a, int stage,
+                                                        const float* m, const float* __restrict__ ms,
+                                                        const float* __restrict__ Hd, float* acc,
+                                                        float* out) {
+    const size_t N = (size_t)a.nx * a.ny * a.nz;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int x = (int)(i % a.nx);
+    int y = (int)((i / a.nx) % a.ny);
+    int z = (int)(i / ((size_t)a.nx * a.ny));
+    float3 c = load3(ms, i, N);
+    // free boundaries: a missing neighbour is replaced by the cell itself
+    float3 lap = make_float3(0.f, 0.f, 0.f);
+    if (a.nx > 1) {
+        float3 l = x > 0 ? load3(ms, i - 1, N) : c;
+        float3 r = x < a.nx - 1 ? load3(ms, i + 1, N) : c;
+        lap.x += a.cx * (l.x + r.x - 2.f * c.x);
+        lap.y += a.cx * (l.y + r.y - 2.f * c.y);
+        lap.z += a.cx * (l.z + r.z - 2.f * c.z);
+    }
+    if (a.ny > 1) {
+        float3 l = y > 0 ? load3(ms, i - a.nx, N) : c;
+        float3 r = y < a.ny - 1 ? load3(ms, i + a.nx, N) : c;
+        lap.x += a.cy * (l.x + r.x - 2.f * c.x);
+        lap.y += a.cy * (l.y + r.y - 2.f * c.y);
+        lap.z += a.cy * (l.z + r.z - 2.f * c.z);
+    }
+    if (a.nz > 1) {
+        size_t pl = (size_t)a.nx * a.ny;
+        float3 l = z > 0 ? load3(ms, i - pl, N) : c;
+        float3 r = z < a.nz - 1 ? load3(ms, i + pl, N) : c;
+        lap.x += a.cz * (l.x + r.x - 2.f * c.x);
+        lap.y += a.cz * (l.y + r.y - 2.f * c.y);
+        lap.z += a.cz * (l.z + r.z - 2.f * c.z);
+    }
+    float3 hd = load3(Hd, i, N);
+    float3 H = make_float3(hd.x + lap.x + a.hz[0], hd.y + lap.y + a.hz[1], hd.z + lap.z + a.hz[2]);
+    float3 k = ll_rhs(c, H, a.gam, a.alpha);
+    float3 m0 = load3(m, i, N);
+    if (stage == 0) {
+        store3(acc, i, N, k);
+        float h = 0.5f * a.dt;
+        store3(out, i, N, make_float3(m0.x + h * k.x, m0.y + h * k.y, m0.z + h * k.z));
+    } else if (stage < 3) {
+        float3 s = load3(acc, i, N);
+        store3(acc, i, N, make_float3(s.x + 2.f * k.x, s.y + 2.f * k.y, s.z + 2.f * k.z));
+        float h = stage == 1 ? 0.5f * a.dt : a.dt;
+        store3(out, i, N, make_float3(m0.x + h * k.x, m0.y + h * k.y, m0.z + h * k.z));
+    } else {
+        float3 s = load3(acc, i, N);
+        float h = a.dt / 6.f;
+        float3 v = make_float3(m0.x + h * (s.x + k.x), m0.y + h * (s.y + k.y), m0.z + h * (s.z + k.z));
+        float inv = rsqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
+        store3(out, i, N, make_float3(v.x * inv, v.y * inv, v.z * inv));
+    }
+}
+
+// ---------------------------------------------------------------- atomistic
+// Eq. (9): M = mu_s mu_B/(a^3 N_S) * sum of the unit spins of the macrocell.
+__global__ __launch_bounds__(256) void macro_average_kernel(AtomArgs a, const float* __restrict__ S,
+                                                            float* __restrict__ Mm) {
+    const int mx = a.nx / a.macro, my = a.ny / a.macro, mz = a.nz / a.macro;
+    const size_t Nm = (size_t)mx * my * mz;
+    const size_t N = (size_t)a.nx * a.ny * a.nz;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Nm) return;
+    int X = (int)(i % mx), Y = (int)((i / mx) % my), Z = (int)(i / ((size_t)mx * my));
+    float3 s = make_float3(0.f, 0.f, 0.f);
+    for (int dz = 0; dz < a.macro; ++dz)
+        for (int dy = 0; dy < a.macro; ++dy) {
+            size_t row = ((size_t)(Z * a.macro + dz) * a.ny + (Y * a.macro + dy)) * a.nx + X * a.macro;
+            for (int dx = 0; dx < a.macro; ++dx) {
+                float3 v = load3(S, row + dx, N);
+                s.x += v.x;
+                s.y += v.y;
+                s.z += v.z;
+            }
+        }
+    store3(Mm, i, Nm, make_float3(a.mscale * s.x, a.mscale * s.y, a.mscale * s.z));
+}
+
+// H = J/(mu0 mu_B mu_s) sum_nn S_j (open boundaries) + H_d(macrocell) + H_zee
+__device__ __forceinline__ float3 atom_field(const AtomArgs& a, const float* __restrict__ S,
+                                             const float* __restrict__ Hdm, size_t i, size_t N,
+                                             int x, int y, int z) {
+    float3 e = make_float3(0.f, 0.f, 0.f);
+    auto add = [&](size_t j) {
+        float3 v = load3(S, j, N);
+        e.x += v.x;
+        e.y += v.y;
+        e.z += v.z;
+    };
+    size_t pl = (size_t)a.nx * a.ny;
+    if (x > 0) add(i - 1);
+    if (x < a.nx - 1) add(i + 1);
+    if (y > 0) add(i - a.nx);
+    if (y < a.ny - 1) add(i + a.nx);
+    if (z > 0) add(i - pl);
+    if (z < a.nz - 1) add(i + pl);
+    const int mx = a.nx / a.macro, my = a.ny / a.macro, mz = a.nz / a.macro;
+    size_t Nm = (size_t)mx * my * mz;
+    size_t im = ((size_t)(z / a.macro) * my + (y / a.macro)) * mx + (x / a.macro);
+    float3 hd = load3(Hdm, im, Nm);
+    return make_float3(a.cex * e.x + hd.x + a.hz[0], a.cex * e.y + hd.y + a.hz[1],
+                       a.cex * e.z + hd.z + a.hz[2]);
+}
+
+__global__ __launch_bounds__(256) void heun_predict_kernel(AtomArgs a, const float* __restrict__ S,
+                                                           const float* __restrict__ Hdm,
+                                                           float* __restrict__ f0,
+                                                           float* __restrict__ Sp) {
+    const size_t N = (size_t)a.nx * a.ny * a.nz;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / ((size_t)a.nx * a.ny));
+    float3 H = atom_field(a, S, Hdm, i, N, x, y, z);
+    float3 s = load3(S, i, N);
+    float3 f = ll_rhs(s, H, a.gam, a.alpha);
+    store3(f0, i, N, f);
+    store3(Sp, i, N, make_float3(s.x + a.dt * f.x, s.y + a.dt * f.y, s.z + a.dt * f.z));
+}
+
+// S <- normalise(S + dt/2 (f0 + f(Sp))); reads neighbours of Sp only, so S may be
+// updated in place.
+__global__ __launch_bounds__(256) void heun_correct_kernel(AtomArgs a, float* S,
+                                                           const float* __restrict__ Sp,
+                                                           const float* __restrict__ f0,
+                                                           const float* __restrict__ Hdm) {
+    const size_t N = (size_t)a.nx * a.ny * a.nz;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / ((size_t)a.nx * a.ny));
+    float3 H = atom_field(a, Sp, Hdm, i, N, x, y, z);
+    float3 sp = load3(Sp, i, N);
+    float3 f1 = ll_rhs(sp, H, a.gam, a.alpha);
+    float3 g = load3(f0, i, N);
+    float3 s = load3(S, i, N);
+    float h = 0.5f * a.dt;
+    float3 v = make_float3(s.x + h * (g.x + f1.x), s.y + h * (g.y + f1.y), s.z + h * (g.z + f1.z));
+    float inv = rsqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
+    store3(S, i, N, make_float3(v.x * inv, v.y * inv, v.z * inv));
+}
+
+unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+int launch_llg_stage(const LLGStageArgs& a, int stage, const float* m, const float* ms,
+                     const float* Hd, float* acc, float* out, hipStream_t stream) {
+    size_t N = (size_t)a.nx * a.ny * a.nz;
+    hipLaunchKernelGGL(llg_stage_kernel, dim3(blocks_for(N)), dim3(256), 0, stream, a, stage, m,
+                       ms, Hd, acc, out);
+    DM_CHECK_LAUNCH();
+    return DEMAG_OK;
+}
+
+int launch_macro_average(const AtomArgs& a, const float* S, float* Mm, hipStream_t stream) {
+    size_t Nm = (size_t)(a.nx / a.macro) * (a.ny / a.macro) * (a.nz / a.macro);
+    hipLaunchKernelGGL(macro_average_kernel, dim3(blocks_for(Nm)), dim3(256), 0, stream, a, S, Mm);
+    DM_CHECK_LAUNCH();
+    return DEMAG_OK;
+}
+
+int launch_heun_predict(const AtomArgs& a, const float* S, const float* Hdm, float* f0, float* Sp,
+                        hipStream_t stream) {
+    size_t N = (size_t)a.nx * a.ny * a.nz;
+    hipLaunchKernelGGL(heun_predict_kernel, dim3(blocks_for(N)), dim3(256), 0, stream, a, S, Hdm,
+                       f0, Sp);
+    DM_CHECK_LAUNCH();
+    return DEMAG_OK;
+}
+
+int launch_heun_correct(const AtomArgs& a, float* S, const float* Sp, const float* f0,
+                        const float* Hdm, hipStream_t stream) {
+    size_t N = (size_t)a.nx * a.ny * a.nz;
+    hipLaunchKernelGGL(heun_correct_kernel, dim3(blocks_for(N)), dim3(256), 0, stream, a, S, Sp,
+                       f0, Hdm);
+    DM_CHECK_LAUNCH();
+    return DEMAG_OK;
+}
+
+}  // namespace dm

@@ -1,0 +1,90 @@
+// engine.h -- internal declarations shared by the HIP sources of the demag engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/demag.h"
+
+namespace dm {
+
+// ---- error reporting --------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+// Evaluate a HIP call; on failure record the message and return DEMAG_EHIP.
+#define DM_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::dm::fail(DEMAG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+#define DM_CHECK_LAUNCH() DM_HIP(hipGetLastError())
+
+// ---- geometry ---------------------------------------------------------------
+struct Geometry {
+    int nx, ny, nz;        // cells
+    int Nx, Ny, Nz;        // padded transform lengths (2n, or 1 when n = 1)
+    int X1, Y1, Z1;        // distinct folded frequencies: N/2 + 1, or 1
+    size_t cells() const { return (size_t)nx * ny * nz; }
+    size_t s1_elems() const { return (size_t)3 * nz * X1 * ny; }   // complex
+    size_t s2_elems() const { return (size_t)3 * nz * X1 * Ny; }   // complex
+    size_t k_elems() const { return (size_t)6 * Z1 * X1 * Y1; }    // real
+};
+
+// Returns DEMAG_OK or an error code (and message) for a mesh the kernels cannot take.
+int make_geometry(int nx, int ny, int nz, Geometry* g);
+
+// ---- FFT stage launchers (stages.hip) -----------------------------------------
+// tw_all: twiddle tables, length-L table exp(-2 pi i t/L) at tw_all + L.
+struct StageArgs {
+    const Geometry* g;
+    const float2* tw_all;
+    float2* S1;            // [3][nz][X1][ny]
+    float2* S2;            // [3][nz][X1][Ny]; == S1 when ny == 1
+    const float* K;        // [6][Z1][X1][Y1]
+    hipStream_t stream;
+};
+int launch_x_forward(const StageArgs& a, const float* M, float scale);
+int launch_y_forward(const StageArgs& a);
+int launch_z_convolve(const StageArgs& a);
+int launch_y_inverse(const StageArgs& a);
+int launch_x_inverse(const StageArgs& a, float* H);
+// Largest transform length the twiddle table must hold for this geometry.
+int twiddle_table_length(const Geometry& g);
+// Fills the host table (2 * Lmax float2) with exp(-2 pi i t/L) at offset L.
+void fill_twiddles(float2* host, int Lmax);
+
+// ---- N^ set-up (tensor.hip) ---------------------------------------------------
+// Computes the packed FP32 kernel K (device) for the geometry and cell, in FP64.
+int compute_kernel(const Geometry& g, double dx, double dy, double dz, float* K,
+                   hipStream_t stream);
+
+// ---- dynamics (dynamics.hip) ----------------------------------------------------
+struct LLGStageArgs {
+    int nx, ny, nz;
+    float cx, cy, cz;      // 2A/(mu0 Ms h_d^2), 0 for an axis with one cell
+    float hz[3];
+    float gam;             // gamma/(1+alpha^2)
+    float alpha;
+    float dt;
+};
+int launch_llg_stage(const LLGStageArgs& a, int stage, const float* m, const float* ms,
+                     const float* Hd, float* acc, float* out, hipStream_t stream);
+
+struct AtomArgs {
+    int nx, ny, nz, macro;
+    float cex;             // J/(mu0 mu_B mu_s)
+    float hz[3];
+    float gam, alpha, dt;
+    float mscale;          // mu_s mu_B/(a^3 N_S)
+};
+int launch_macro_average(const AtomArgs& a, const float* S, float* Mm, hipStream_t stream);
+int launch_heun_predict(const AtomArgs& a, const float* S, const float* Hdm, float* f0,
+                        float* Sp, hipStream_t stream);
+int launch_heun_correct(const AtomArgs& a, float* S, const float* Sp, const float* f0,
+                        const float* Hdm, hipStream_t stream);
+
+}  // namespace dm

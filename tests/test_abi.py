@@ -1,0 +1,61 @@
+"""Host-side checks of the C ABI (no GPU needed): the shared library loads, exports
+every symbol include/demag.h declares, and rejects bad arguments before any
+device work."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2308_08447_amd as pkg
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "demag.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_]+)\s*\([^;{]*\)\s*;", text)) - {"sizeof"})
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pkg.load()
+    names = declared_functions()
+    assert len(names) >= 10, names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(pkg.EXPORTS) == set(names)
+
+
+def test_plan_bytes_and_validation_on_host():
+    assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9)) > 0
+    assert pkg.demag_plan_bytes((30, 32, 4, 4e-9, 4e-9, 4e-9)) == 0
+    assert pkg.demag_plan_bytes((32, 32, 256, 4e-9, 4e-9, 4e-9)) == 0
+    assert pkg.demag_plan_bytes((32, 32, 4, -4e-9, 4e-9, 4e-9)) == 0
+    assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=7) == 0
+    with pytest.raises(pkg.DemagError) as e:
+        pkg.demag_setup((24, 32, 4, 4e-9, 4e-9, 4e-9))
+    assert e.value.status == pkg.DEMAG_EUNSUPPORTED
+    with pytest.raises(pkg.DemagError) as e:
+        pkg.demag_setup((0, 32, 4, 4e-9, 4e-9, 4e-9))
+    assert e.value.status == pkg.DEMAG_EINVAL
+    with pytest.raises(pkg.DemagError) as e:
+        pkg.demag_setup((8, 8, 8, 4e-9, float("nan"), 4e-9))
+    assert e.value.status == pkg.DEMAG_EINVAL
+    with pytest.raises(pkg.DemagError) as e:
+        pkg.atom_setup((16, 16, 8, 0.4e-9, 3))
+    assert e.value.status == pkg.DEMAG_EINVAL
+    lib = pkg.load()
+    assert lib.demag_field(None, None, None, None) == pkg.DEMAG_EINVAL
+    assert lib.llg_step(None, None, None, 1e-13, 1, None) == pkg.DEMAG_EINVAL
+    assert lib.demag_destroy(None) == pkg.DEMAG_EINVAL
+    assert b"NULL" in lib.demag_last_error()
+
+
+def test_plan_bytes_formula():
+    nx, ny, nz = 512, 512, 16
+    X1, Y1, Z1 = nx + 1, ny + 1, nz + 1
+    expect = 6 * Z1 * X1 * Y1 * 4 + 2 * 2 * ny * 8 + 3 * nz * X1 * ny * 8 + 3 * nz * X1 * 2 * ny * 8
+    assert pkg.demag_plan_bytes((nx, ny, nz, 4e-9, 4e-9, 4e-9)) == expect

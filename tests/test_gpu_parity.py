@@ -1,0 +1,241 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerance: relative L2 <= 2e-5 per field component for the demagnetizing field
+(FP32 FFT stages; the expected error is ~1e-7).  Inputs are the same seeded FP32
+arrays on both sides (workloads.magnetisation), so input rounding is not error.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import atomistic as oatom
+from oracle import demag as odemag
+from oracle import llg as ollg
+
+pytestmark = pytest.mark.gpu
+
+TOL = 2e-5
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _gpu_field(pkg, torch, n, cell, M):
+    nx, ny, nz = n
+    plan = pkg.demag_setup((nx, ny, nz) + tuple(cell))
+    try:
+        Md = torch.from_numpy(M).cuda()
+        Hd = torch.empty_like(Md)
+        pkg.demag_field(plan, Md, Hd)
+        torch.cuda.synchronize()
+        return Hd.cpu().numpy().astype(np.float64)
+    finally:
+        pkg.demag_destroy(plan)
+
+
+SHAPES = [
+    (32, 32, 4), (1, 1, 1), (2, 1, 1), (1, 8, 1), (8, 1, 1), (16, 1, 4), (4, 4, 2),
+    (8, 8, 8), (64, 32, 8), (128, 64, 2), (32, 64, 1), (8, 4, 64), (4, 4, 128),
+    (256, 16, 2), (16, 256, 1), (2048, 4, 1), (4, 2048, 2),
+]
+
+
+@pytest.mark.parametrize("n", SHAPES, ids=lambda n: "x".join(map(str, n)))
+def test_field_matches_oracle(gpu_lib, torch_dev, n):
+    import paper_2308_08447_amd as pkg
+    _say("demag_field parity", n)
+    cell = W.CELL_4NM
+    M = W.magnetisation(n, seed=sum(n))
+    H = _gpu_field(pkg, torch_dev, n, cell, M)
+    Href = odemag.demag_fft(M.astype(np.float64), cell)
+    errs = odemag.rel_l2_per_field(H, Href)
+    _say("  rel-L2 per field", errs)
+    assert max(errs) <= TOL, errs
+
+
+def test_field_matches_direct_sum_small(gpu_lib, torch_dev):
+    import paper_2308_08447_amd as pkg
+    n, cell = (8, 8, 4), (4e-9, 3e-9, 2e-9)
+    _say("demag_field vs direct sum", n, cell)
+    M = W.magnetisation(n, seed=3)
+    H = _gpu_field(pkg, torch_dev, n, cell, M)
+    Href = odemag.demag_direct(M.astype(np.float64), cell)
+    assert max(odemag.rel_l2_per_field(H, Href)) <= TOL
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_demag_small_config(gpu_lib, torch_dev, seed):
+    """32x32x4 cells of 4 nm, Ms = 8e5, seeded random unit M: FP64 oracle and direct sum."""
+    import paper_2308_08447_amd as pkg
+    n, cell = W.DEMAG_SMALL["n"], W.DEMAG_SMALL["cell"]
+    _say("demag 32x32x4 seed", seed)
+    M = W.magnetisation(n, seed)
+    H = _gpu_field(pkg, torch_dev, n, cell, M)
+    Href = odemag.demag_fft(M.astype(np.float64), cell)
+    errs = odemag.rel_l2_per_field(H, Href)
+    _say("  rel-L2 per field", errs)
+    assert max(errs) <= TOL
+    targets = np.array([[0, 0, 0], [31, 31, 3], [13, 7, 2], [31, 0, 1]])
+    direct = odemag.demag_at(M.astype(np.float64), cell, targets)
+    for t, (x, y, z) in enumerate(targets):
+        np.testing.assert_allclose(H[:, z, y, x], direct[:, t], rtol=0,
+                                   atol=TOL * np.abs(Href).max())
+
+
+@pytest.mark.parametrize("n,cell", [((16, 8, 4), (4e-9, 4e-9, 4e-9)), ((8, 1, 2), (1e-9, 2e-9, 3e-9)),
+                                    ((1, 1, 1), (2e-9, 2e-9, 2e-9)), ((32, 32, 4), W.CELL_4NM)])
+def test_kernel_matches_oracle_spectrum(gpu_lib, torch_dev, n, cell):
+    """The packed FP32 kernel equals -N^/(NxNyNz) of the oracle's transformed tensor."""
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    _say("kernel spectrum", n, cell)
+    nx, ny, nz = n
+    plan = pkg.demag_setup((nx, ny, nz) + tuple(cell))
+    try:
+        shape = pkg.kernel_shape(n)
+        K = torch.empty(int(np.prod(shape)), dtype=torch.float32, device="cuda")
+        pkg.demag_get_kernel(plan, K, K.numel())
+        torch.cuda.synchronize()
+        K = K.cpu().numpy().reshape(shape).astype(np.float64)
+    finally:
+        pkg.demag_destroy(plan)
+    op = odemag.DemagFFT(n, cell)
+    Nx, Ny, Nz = op.N
+    _, Z1, X1, Y1 = shape
+    for c in range(6):
+        # oracle rfftn output is [kz][ky][kx] with kx <= Nx/2
+        ref = -op.Khat[c].real[:Z1, :Y1, :X1].transpose(0, 2, 1) / (Nx * Ny * Nz)
+        scale = np.abs(ref).max()
+        assert np.abs(K[c] - ref).max() <= 1e-6 * scale, c
+
+
+def test_field_full_thin_film(gpu_lib, torch_dev):
+    """512x512x16 (4 nm cubes), seeded random M: whole field against the FP64 oracle."""
+    import paper_2308_08447_amd as pkg
+    n, cell = W.THIN_FILM["n"], W.THIN_FILM["cell"]
+    _say("demag 512x512x16 full-field parity")
+    M = W.magnetisation(n, 0)
+    H = _gpu_field(pkg, torch_dev, n, cell, M)
+    Href = odemag.DemagFFT(n, cell, workers=8)(M.astype(np.float64))
+    errs = odemag.rel_l2_per_field(H, Href)
+    _say("  rel-L2 per field", errs)
+    assert max(errs) <= TOL
+
+
+def test_field_is_deterministic(gpu_lib, torch_dev):
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    n = (64, 64, 8)
+    _say("determinism", n)
+    plan = pkg.demag_setup(n + W.CELL_4NM)
+    try:
+        M = torch.from_numpy(W.magnetisation(n, 5)).cuda()
+        H1, H2 = torch.empty_like(M), torch.empty_like(M)
+        pkg.demag_field(plan, M, H1)
+        pkg.demag_field(plan, M, H2)
+        torch.cuda.synchronize()
+        assert torch.equal(H1, H2)
+    finally:
+        pkg.demag_destroy(plan)
+
+
+def test_abi_rejects_bad_arguments(gpu_lib, torch_dev):
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    plan = pkg.demag_setup((8, 8, 2) + W.CELL_4NM)
+    try:
+        M = torch.zeros(3 * 8 * 8 * 2, device="cuda")
+        with pytest.raises(pkg.DemagError) as e:
+            pkg.demag_field(plan, M, M)
+        assert e.value.status == pkg.DEMAG_EINVAL
+        with pytest.raises(pkg.DemagError):
+            pkg.llg_step(plan, M, (8e5, 1.3e-11, 0.1, 2.21e5, (0, 0, 0)), 1e-13, -1)
+    finally:
+        pkg.demag_destroy(plan)
+
+
+# ------------------------------------------------------------------ LLG (RK4)
+@pytest.mark.parametrize("n,steps", [((16, 8, 2), 1), ((16, 8, 2), 10), ((32, 32, 4), 10),
+                                     ((1, 1, 1), 20), ((64, 1, 1), 5)])
+def test_llg_matches_oracle(gpu_lib, torch_dev, n, steps):
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    _say("llg_step parity", n, steps)
+    nx, ny, nz = n
+    m0 = W.unit_vectors((nz, ny, nx), seed=11)
+    alpha, dt, Hz = 0.02, 1e-13, (1e4, -2e4, 3e4)
+    plan = pkg.demag_setup(n + W.CELL_4NM)
+    try:
+        m = torch.from_numpy(m0).cuda()
+        pkg.llg_step(plan, m, (W.MS, W.A_EX, alpha, ollg.GAMMA, Hz), dt, steps)
+        torch.cuda.synchronize()
+        got = m.cpu().numpy().astype(np.float64)
+    finally:
+        pkg.demag_destroy(plan)
+    prob = ollg.LLG(n, W.CELL_4NM, W.MS, W.A_EX, alpha, Hzee=Hz)
+    ref = prob.run(m0.astype(np.float64), dt, steps)
+    err = odemag.rel_l2(got, ref)
+    _say("  rel-L2 of m", err)
+    assert err <= TOL
+    np.testing.assert_allclose(np.linalg.norm(got, axis=0), 1.0, atol=1e-6)
+
+
+def test_llg_thin_film_one_step(gpu_lib, torch_dev):
+    """512x512x16 thin film (A = 1.3e-11, alpha = 0.02, dt = 1e-13): one RK4 step."""
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    cfg = W.THIN_FILM
+    n = cfg["n"]
+    _say("llg 512x512x16 one step")
+    m0 = W.unit_vectors((n[2], n[1], n[0]), seed=0)
+    plan = pkg.demag_setup(n + cfg["cell"])
+    try:
+        m = torch.from_numpy(m0).cuda()
+        pkg.llg_step(plan, m, (cfg["Ms"], cfg["A"], cfg["alpha"], ollg.GAMMA, (0, 0, 0)), cfg["dt"], 1)
+        torch.cuda.synchronize()
+        got = m.cpu().numpy().astype(np.float64)
+    finally:
+        pkg.demag_destroy(plan)
+    prob = ollg.LLG(n, cfg["cell"], cfg["Ms"], cfg["A"], cfg["alpha"], workers=8)
+    ref = prob.rk4_step(m0.astype(np.float64), cfg["dt"])
+    # compare the change of m (the step itself), the stricter measure
+    d_got, d_ref = got - m0, ref - m0
+    err = odemag.rel_l2(d_got, d_ref)
+    _say("  rel-L2 of the step increment", err, " of m", odemag.rel_l2(got, ref))
+    assert odemag.rel_l2(got, ref) <= TOL
+    assert err <= 1e-3
+
+
+# ------------------------------------------------------------------ atomistic
+@pytest.mark.parametrize("n,macro,steps", [((16, 16, 8), 4, 1), ((16, 16, 8), 4, 5), ((8, 8, 8), 2, 3),
+                                           ((4, 4, 4), 4, 2)])
+def test_atomistic_matches_oracle(gpu_lib, torch_dev, n, macro, steps):
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    _say("atom_step parity", n, macro, steps)
+    cfg = W.ATOMISTIC
+    nx, ny, nz = n
+    S0 = W.unit_vectors((nz, ny, nx), seed=21)
+    hz = (0.0, 0.0, 5e5)
+    plan = pkg.atom_setup((nx, ny, nz, cfg["a"], macro))
+    try:
+        S = torch.from_numpy(S0).cuda()
+        pkg.atom_step(plan, S, (cfg["J"], cfg["mu_s"], cfg["alpha"], ollg.GAMMA, hz), cfg["dt"], steps)
+        torch.cuda.synchronize()
+        got = S.cpu().numpy().astype(np.float64)
+    finally:
+        pkg.atom_destroy(plan)
+    prob = oatom.Atomistic(n, cfg["a"], macro, cfg["J"], cfg["mu_s"], cfg["alpha"], Hzee=hz)
+    ref = prob.run(S0.astype(np.float64), cfg["dt"], steps)
+    err = odemag.rel_l2(got, ref)
+    _say("  rel-L2 of S", err, " increment", odemag.rel_l2(got - S0, ref - S0))
+    assert err <= TOL
