@@ -71,6 +71,13 @@ def load(path=None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"HIP library not built: {p} (run python -m paper_2308_08447_amd.build)")
+    # A process must hold exactly one HIP runtime.  PyTorch wheels bundle their own
+    # libamdhip64 under the same soname; loading torch first makes the library bind
+    # to that copy instead of pulling a second runtime in from /opt/rocm.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(p)
     vp, sz = ctypes.c_void_p, ctypes.c_size_t
     P = ctypes.POINTER

@@ -110,6 +110,19 @@ struct atom_plan {
     float* f0 = nullptr;    // predictor slope (3 N)
 };
 
+// hipMalloc with the HIP error text in the failure message
+static int dev_alloc(void** p, size_t bytes, const char* what) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? DEMAG_ENOMEM : DEMAG_EHIP,
+                    std::string("hipMalloc(") + what + ", " + std::to_string(bytes) +
+                        " B): " + hipGetErrorString(e));
+    }
+    return DEMAG_OK;
+}
+
 static void free_plan(demag_plan* p) {
     if (!p) return;
     free_timing(p);
@@ -160,20 +173,18 @@ int demag_setup(const demag_mesh* mesh, uint32_t flags, void* stream, demag_plan
         free_plan(p);
         return code;
     };
-    if (hipMalloc(&p->K, g.k_elems() * sizeof(float)) != hipSuccess ||
-        hipMalloc(&p->S1, g.s1_elems() * sizeof(float2)) != hipSuccess)
-        return bail(fail(DEMAG_ENOMEM, "device allocation failed (kernel / S1)"));
+    if ((rc = dev_alloc((void**)&p->K, g.k_elems() * sizeof(float), "kernel")) ||
+        (rc = dev_alloc((void**)&p->S1, g.s1_elems() * sizeof(float2), "S1")))
+        return bail(rc);
     if (g.ny > 1) {
-        if (hipMalloc(&p->S2, g.s2_elems() * sizeof(float2)) != hipSuccess)
-            return bail(fail(DEMAG_ENOMEM, "device allocation failed (S2)"));
+        if ((rc = dev_alloc((void**)&p->S2, g.s2_elems() * sizeof(float2), "S2"))) return bail(rc);
     } else {
         p->S2 = p->S1;
     }
     int Lmax = twiddle_table_length(g);
     std::vector<float2> tw((size_t)2 * Lmax);
     fill_twiddles(tw.data(), Lmax);
-    if (hipMalloc(&p->tw, tw.size() * sizeof(float2)) != hipSuccess)
-        return bail(fail(DEMAG_ENOMEM, "device allocation failed (twiddles)"));
+    if ((rc = dev_alloc((void**)&p->tw, tw.size() * sizeof(float2), "twiddles"))) return bail(rc);
     if (hipMemcpyAsync(p->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, s) !=
         hipSuccess)
         return bail(fail(DEMAG_EHIP, "twiddle upload failed"));
@@ -280,8 +291,8 @@ int llg_step(demag_plan* plan, float* m, const llg_params* prm, double dt, int32
     const Geometry& g = plan->g;
     const size_t N3 = 3 * g.cells();
     if (!plan->rk) {
-        if (hipMalloc(&plan->rk, 4 * N3 * sizeof(float)) != hipSuccess)
-            return fail(DEMAG_ENOMEM, "device allocation failed (RK4 buffers)");
+        int rc = dev_alloc((void**)&plan->rk, 4 * N3 * sizeof(float), "RK4 buffers");
+        if (rc) return rc;
     }
     float* Hd = plan->rk;
     float* bufA = plan->rk + N3;
@@ -355,13 +366,13 @@ int atom_setup(const atom_mesh* mesh, uint32_t flags, void* stream, atom_plan** 
     }
     size_t N3 = (size_t)3 * mesh->nx * mesh->ny * mesh->nz;
     size_t M3 = (size_t)3 * dm_mesh.nx * dm_mesh.ny * dm_mesh.nz;
-    if (hipMalloc(&p->Mm, M3 * sizeof(float)) != hipSuccess ||
-        hipMalloc(&p->Hd0, M3 * sizeof(float)) != hipSuccess ||
-        hipMalloc(&p->Hd1, M3 * sizeof(float)) != hipSuccess ||
-        hipMalloc(&p->Sp, N3 * sizeof(float)) != hipSuccess ||
-        hipMalloc(&p->f0, N3 * sizeof(float)) != hipSuccess) {
+    if ((rc = dev_alloc((void**)&p->Mm, M3 * sizeof(float), "macrocell M")) ||
+        (rc = dev_alloc((void**)&p->Hd0, M3 * sizeof(float), "macrocell H_d")) ||
+        (rc = dev_alloc((void**)&p->Hd1, M3 * sizeof(float), "macrocell H_d'")) ||
+        (rc = dev_alloc((void**)&p->Sp, N3 * sizeof(float), "predictor spins")) ||
+        (rc = dev_alloc((void**)&p->f0, N3 * sizeof(float), "predictor slope"))) {
         free_atom(p);
-        return fail(DEMAG_ENOMEM, "device allocation failed (atomistic buffers)");
+        return rc;
     }
     *out = p;
     return DEMAG_OK;

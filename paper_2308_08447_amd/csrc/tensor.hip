@@ -277,6 +277,7 @@ int compute_kernel(const Geometry& g, double dx, double dy, double dz, float* K,
     DM_HIP(hipMalloc(&T0.p, 6 * n0 * sizeof(double)));
     DM_HIP(hipMalloc(&T1.p, 6 * n1 * sizeof(double)));
     DM_HIP(hipMalloc(&T2.p, 6 * n2 * sizeof(double)));
+    // (a failed set-up allocation is reported as DEMAG_EHIP with the HIP error text)
 
     // trig matrices: [axis][parity] blocks
     std::vector<double> host;
