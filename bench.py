@@ -100,6 +100,8 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     plan = pkg.demag_setup(n + cell, stream=stream)
+    pkg.demag_autotune(plan, stream)
+    variants = [pkg.demag_get_variant(plan, st) for st in range(5)]
     m0 = torch.from_numpy(W.unit_vectors((n[2], n[1], n[0]), seed=0)).to(dev)
     m = m0.clone()
     params = (cfg["Ms"], cfg["A"], cfg["alpha"], 2.21276e5, (0.0, 0.0, 0.0))
@@ -107,7 +109,8 @@ def main():
     for _ in range(args.warmup):
         pkg.llg_step(plan, m, params, cfg["dt"], 1, stream)
     torch.cuda.synchronize()
-    pkg.demag_timing_enable(plan, 4 * args.steps)
+    nch = pkg.demag_get_chunks(plan)
+    pkg.demag_timing_enable(plan, 4 * args.steps * nch)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -134,13 +137,18 @@ def main():
 
     ms_per_step = 1e3 * elapsed / args.steps
     value = 4 * cells * args.steps / elapsed / 1e9
-    nbytes = stage_bytes(n)
+    nbytes = stage_bytes(n)   # per H_d evaluation (per RK stage for "llg")
+    evals = 4 * args.steps
     per_stage = {}
     for name, (tot_ms, cnt) in stages.items():
         if cnt:
+            # the y/z stages run once per chunk: bytes per launch = bytes per evaluation / chunks
+            per_launch = nbytes[name] * evals / cnt
             avg = tot_ms / cnt
             per_stage[name] = {"avg_us": round(1e3 * avg, 2), "launches": cnt,
-                               "GB_per_s": round(nbytes[name] / (avg * 1e-3) / 1e9, 1)}
+                               "bytes_per_launch": int(per_launch),
+                               "GB_per_s": round(per_launch / (avg * 1e-3) / 1e9, 1),
+                               "us_per_eval": round(1e3 * tot_ms / evals, 2)}
     dom = max(per_stage, key=lambda k: per_stage[k]["avg_us"] * per_stage[k]["launches"])
     achieved = per_stage[dom]["GB_per_s"]
     b5 = sum(v for k, v in nbytes.items() if k != "llg")
@@ -159,7 +167,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "mesh": list(n), "cell_m": list(cell),
-                   "hd_evals_per_step": 4, "global_batch": 1, "parallelism": "none"},
+                   "hd_evals_per_step": 4, "global_batch": 1, "parallelism": "none",
+                   "stage_variants": variants, "yz_chunks": nch},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None},

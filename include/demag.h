@@ -178,6 +178,31 @@ int demag_timing_enable(demag_plan* plan, int32_t max_records);
  */
 int demag_timing_read(demag_plan* plan, double* total_ms, int32_t* launches);
 
+/* ---- tile-shape variants and autotuning ---------------------------------- */
+/*
+ * Each FFT stage (DEMAG_STAGE_X_FWD .. DEMAG_STAGE_X_INV) has DEMAG_NVARIANTS
+ * tile shapes (how many rows, lines or columns one workgroup transforms).  All
+ * variants produce bit-identical results; they differ only in speed.
+ * demag_autotune times every variant of every stage on the plan's own buffers
+ * (HIP events, 5 launches each; synchronises `stream`), keeps the fastest and
+ * remembers the choice for later plans of the same mesh size in this process.
+ */
+enum { DEMAG_NVARIANTS = 3 };
+int demag_autotune(demag_plan* plan, void* stream);
+
+/*
+ * The y FFT, z convolution and y IFFT run chunk by chunk over the n_x + 1 kx
+ * planes of the spectrum through a re-used buffer of at most 128 MB (so a
+ * chunk's spectra stay in the 256 MB Infinity Cache).  demag_autotune also picks
+ * the number of chunks; demag_set_chunks sets it explicitly (at least
+ * ceil((n_x + 1) / planes the buffer holds), at most n_x + 1).  The result does
+ * not depend on the chunking.
+ */
+int demag_set_chunks(demag_plan* plan, int32_t nchunks);
+int demag_get_chunks(demag_plan* plan, int32_t* nchunks);
+int demag_set_variant(demag_plan* plan, int32_t stage, int32_t variant);
+int demag_get_variant(demag_plan* plan, int32_t stage, int32_t* variant);
+
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char* demag_last_error(void);
 

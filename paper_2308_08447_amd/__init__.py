@@ -29,8 +29,10 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EUNSUPPORTED", -4: "EH
 EXPORTS = (
     "demag_setup", "demag_field", "demag_plan_bytes", "demag_get_kernel", "demag_destroy",
     "llg_step", "atom_setup", "atom_step", "atom_destroy", "demag_timing_enable",
-    "demag_timing_read", "demag_last_error",
+    "demag_timing_read", "demag_autotune", "demag_set_variant", "demag_get_variant",
+    "demag_set_chunks", "demag_get_chunks", "demag_last_error",
 )
+NVARIANTS = 3
 STAGES = ("x_fwd", "y_fwd", "z_conv", "y_inv", "x_inv", "llg")
 
 
@@ -93,6 +95,11 @@ def load(path=None):
         "atom_destroy": ([vp], ctypes.c_int),
         "demag_timing_enable": ([vp, ctypes.c_int32], ctypes.c_int),
         "demag_timing_read": ([vp, P(ctypes.c_double), P(ctypes.c_int32)], ctypes.c_int),
+        "demag_autotune": ([vp, vp], ctypes.c_int),
+        "demag_set_variant": ([vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+        "demag_get_variant": ([vp, ctypes.c_int32, P(ctypes.c_int32)], ctypes.c_int),
+        "demag_set_chunks": ([vp, ctypes.c_int32], ctypes.c_int),
+        "demag_get_chunks": ([vp, P(ctypes.c_int32)], ctypes.c_int),
         "demag_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -178,6 +185,30 @@ def demag_timing_read(plan):
     cnt = (ctypes.c_int32 * n)()
     _check(load().demag_timing_read(plan, ms, cnt))
     return {STAGES[i]: (ms[i], cnt[i]) for i in range(n)}
+
+
+def demag_autotune(plan, stream=None):
+    return _check(load().demag_autotune(plan, _stream(stream)))
+
+
+def demag_set_variant(plan, stage, variant):
+    return _check(load().demag_set_variant(plan, stage, variant))
+
+
+def demag_get_variant(plan, stage):
+    v = ctypes.c_int32()
+    _check(load().demag_get_variant(plan, stage, ctypes.byref(v)))
+    return v.value
+
+
+def demag_set_chunks(plan, nchunks):
+    return _check(load().demag_set_chunks(plan, nchunks))
+
+
+def demag_get_chunks(plan):
+    v = ctypes.c_int32()
+    _check(load().demag_get_chunks(plan, ctypes.byref(v)))
+    return v.value
 
 
 def atom_setup(mesh, flags=DEMAG_FP32, stream=None):

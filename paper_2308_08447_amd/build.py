@@ -21,6 +21,9 @@ FLAGS = [
     f"--offload-arch={ARCH}",
     # packed FP32 ops (v_pk_*_f32) stay disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit multiply-add contraction: the kernels spell out every fmaf, so
+    # their rounding does not depend on unrolling (tile variants agree bitwise)
+    "-ffp-contract=off",
     "-Wno-unused-command-line-argument",
 ]
 

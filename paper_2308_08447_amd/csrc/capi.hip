@@ -9,6 +9,9 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <array>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "engine.h"
@@ -64,7 +67,9 @@ struct demag_plan {
     float* K = nullptr;
     float2* tw = nullptr;
     float2* S1 = nullptr;
-    float2* S2 = nullptr;   // == S1 when ny == 1
+    float2* S2 = nullptr;   // chunk buffer of xc kx planes; == S1 (xc = X1) when ny == 1
+    int xc = 1;             // kx planes S2 holds
+    int nch = 1;            // chunks the y/z stages are split into (>= ceil(X1 / xc))
     // RK4 stage buffers (lazily allocated): H, A, B, acc, each 3 N floats
     float* rk = nullptr;
     int device = 0;
@@ -72,7 +77,18 @@ struct demag_plan {
     int timing_cap = 0;
     std::vector<hipEvent_t> ev[DEMAG_NSTAGES];   // 2 * timing_cap events per stage
     int timing_n[DEMAG_NSTAGES] = {};
+    int variant[5] = {1, 1, 1, 1, 1};   // tile-shape variant of each FFT stage
 };
+
+struct Tuned {
+    std::array<int, 5> variant;
+    int nch;
+};
+
+// Variants picked by demag_autotune, shared by every plan of the same mesh size in
+// this process.
+static std::mutex g_tune_mu;
+static std::map<std::array<int, 3>, Tuned> g_tuned;
 
 static void free_timing(demag_plan* p) {
     for (int s = 0; s < DEMAG_NSTAGES; ++s) {
@@ -134,11 +150,24 @@ static void free_plan(demag_plan* p) {
     delete p;
 }
 
+// S2 holds the y/z spectra of a chunk of kx planes.  Its size is capped so a
+// chunk's spectra stay resident in the 256 MB Infinity Cache while the chunk's
+// y FFT, z convolution and y IFFT run back to back.
+static constexpr size_t S2_CHUNK_BYTES = (size_t)128 << 20;
+
+static int s2_planes(const Geometry& g) {
+    if (g.ny == 1) return g.X1;
+    size_t plane = (size_t)3 * g.nz * g.Ny * sizeof(float2);
+    size_t planes = S2_CHUNK_BYTES / plane;
+    if (planes < 1) planes = 1;
+    return planes >= (size_t)g.X1 ? g.X1 : (int)planes;
+}
+
 static size_t plan_bytes(const Geometry& g) {
     size_t b = g.k_elems() * sizeof(float);
     b += (size_t)2 * twiddle_table_length(g) * sizeof(float2);
     b += g.s1_elems() * sizeof(float2);
-    if (g.ny > 1) b += g.s2_elems() * sizeof(float2);
+    if (g.ny > 1) b += (size_t)3 * g.nz * s2_planes(g) * g.Ny * sizeof(float2);
     return b;
 }
 
@@ -176,8 +205,11 @@ int demag_setup(const demag_mesh* mesh, uint32_t flags, void* stream, demag_plan
     if ((rc = dev_alloc((void**)&p->K, g.k_elems() * sizeof(float), "kernel")) ||
         (rc = dev_alloc((void**)&p->S1, g.s1_elems() * sizeof(float2), "S1")))
         return bail(rc);
+    p->xc = s2_planes(g);
+    p->nch = (g.X1 + p->xc - 1) / p->xc;
     if (g.ny > 1) {
-        if ((rc = dev_alloc((void**)&p->S2, g.s2_elems() * sizeof(float2), "S2"))) return bail(rc);
+        if ((rc = dev_alloc((void**)&p->S2, (size_t)3 * g.nz * p->xc * g.Ny * sizeof(float2), "S2")))
+            return bail(rc);
     } else {
         p->S2 = p->S1;
     }
@@ -190,6 +222,14 @@ int demag_setup(const demag_mesh* mesh, uint32_t flags, void* stream, demag_plan
         return bail(fail(DEMAG_EHIP, "twiddle upload failed"));
     rc = compute_kernel(g, mesh->dx, mesh->dy, mesh->dz, p->K, s);
     if (rc) return bail(rc);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find({g.nx, g.ny, g.nz});
+        if (it != g_tuned.end()) {
+            for (int i = 0; i < 5; ++i) p->variant[i] = it->second.variant[i];
+            p->nch = it->second.nch;
+        }
+    }
     *out = p;
     return DEMAG_OK;
 }
@@ -202,24 +242,42 @@ int demag_destroy(demag_plan* plan) {
 
 }  // extern "C"
 
+static StageArgs stage_args(demag_plan* p, hipStream_t s) {
+    StageArgs a{&p->g, p->tw, p->S1, p->S2, p->K, s, {}, p->xc};
+    for (int i = 0; i < 5; ++i) a.variant[i] = p->variant[i];
+    return a;
+}
+
+// x R2C over the whole mesh; then, chunk by chunk of kx planes, y FFT -> z
+// convolution -> y IFFT through the chunk buffer; then x C2R.
 static int run_field(demag_plan* p, const float* M, float* H, float scale, hipStream_t s) {
-    StageArgs a{&p->g, p->tw, p->S1, p->S2, p->K, s};
+    const Geometry& g = p->g;
+    StageArgs a = stage_args(p, s);
     int rc;
     {
         StageTimer t(p, DEMAG_STAGE_X_FWD, s);
         if ((rc = launch_x_forward(a, M, scale))) return rc;
     }
-    if (p->g.ny > 1) {
-        StageTimer t(p, DEMAG_STAGE_Y_FWD, s);
-        if ((rc = launch_y_forward(a))) return rc;
-    }
-    {
+    if (g.ny == 1) {
         StageTimer t(p, DEMAG_STAGE_Z_CONV, s);
-        if ((rc = launch_z_convolve(a))) return rc;
-    }
-    if (p->g.ny > 1) {
-        StageTimer t(p, DEMAG_STAGE_Y_INV, s);
-        if ((rc = launch_y_inverse(a))) return rc;
+        if ((rc = launch_z_convolve(a, 0, g.X1))) return rc;
+    } else {
+        const int per = (g.X1 + p->nch - 1) / p->nch;
+        for (int k0 = 0; k0 < g.X1; k0 += per) {
+            const int nk = per < g.X1 - k0 ? per : g.X1 - k0;
+            {
+                StageTimer t(p, DEMAG_STAGE_Y_FWD, s);
+                if ((rc = launch_y_forward(a, k0, nk))) return rc;
+            }
+            {
+                StageTimer t(p, DEMAG_STAGE_Z_CONV, s);
+                if ((rc = launch_z_convolve(a, k0, nk))) return rc;
+            }
+            {
+                StageTimer t(p, DEMAG_STAGE_Y_INV, s);
+                if ((rc = launch_y_inverse(a, k0, nk))) return rc;
+            }
+        }
     }
     StageTimer t(p, DEMAG_STAGE_X_INV, s);
     return launch_x_inverse(a, H);
@@ -232,6 +290,129 @@ int demag_field(demag_plan* plan, const float* M, float* H, void* stream) {
     if (!M || !H) return fail(DEMAG_EINVAL, "M and H must be non-NULL device pointers");
     if ((const void*)M == (const void*)H) return fail(DEMAG_EINVAL, "H must not alias M");
     return run_field(plan, M, H, 1.0f, (hipStream_t)stream);
+}
+
+int demag_set_variant(demag_plan* plan, int32_t stage, int32_t variant) {
+    if (!plan) return fail(DEMAG_EINVAL, "plan is NULL");
+    if (stage < 0 || stage > DEMAG_STAGE_X_INV) return fail(DEMAG_EINVAL, "stage must be an FFT stage (0..4)");
+    if (variant < 0 || variant >= NVARIANTS) return fail(DEMAG_EINVAL, "variant out of range");
+    plan->variant[stage] = variant;
+    return DEMAG_OK;
+}
+
+int demag_get_variant(demag_plan* plan, int32_t stage, int32_t* variant) {
+    if (!plan || !variant) return fail(DEMAG_EINVAL, "NULL argument");
+    if (stage < 0 || stage > DEMAG_STAGE_X_INV) return fail(DEMAG_EINVAL, "stage must be an FFT stage (0..4)");
+    *variant = plan->variant[stage];
+    return DEMAG_OK;
+}
+
+int demag_set_chunks(demag_plan* plan, int32_t nchunks) {
+    if (!plan) return fail(DEMAG_EINVAL, "plan is NULL");
+    const Geometry& g = plan->g;
+    const int nmin = (g.X1 + plan->xc - 1) / plan->xc;
+    if (nchunks < nmin || nchunks > g.X1)
+        return fail(DEMAG_EINVAL, "chunk count out of range [ceil(X1 / planes held), X1]");
+    plan->nch = g.ny == 1 ? 1 : nchunks;
+    return DEMAG_OK;
+}
+
+int demag_get_chunks(demag_plan* plan, int32_t* nchunks) {
+    if (!plan || !nchunks) return fail(DEMAG_EINVAL, "NULL argument");
+    *nchunks = plan->nch;
+    return DEMAG_OK;
+}
+
+int demag_autotune(demag_plan* plan, void* stream) {
+    if (!plan) return fail(DEMAG_EINVAL, "plan is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const Geometry& g = plan->g;
+    const size_t n3 = 3 * g.cells();
+    float* M = nullptr;
+    int rc = dev_alloc((void**)&M, 2 * n3 * sizeof(float), "autotune fields");
+    if (rc) return rc;
+    float* H = M + n3;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(M);
+    };
+    if (hipMemsetAsync(M, 0, 2 * n3 * sizeof(float), s) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(DEMAG_EHIP, "autotune set-up failed");
+    }
+    const int saved_cap = plan->timing_cap;
+    plan->timing_cap = 0;  // no per-stage events while tuning
+    // times `reps` runs of fn on the stream
+    auto time_it = [&](auto&& fn, int reps, double* ms_out) -> int {
+        int r;
+        if ((r = fn())) return r;  // warm-up
+        (void)hipEventRecord(e0, s);
+        for (int i = 0; i < reps; ++i)
+            if ((r = fn())) return r;
+        (void)hipEventRecord(e1, s);
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return fail(DEMAG_EHIP, "autotune timing failed");
+        *ms_out = ms;
+        return DEMAG_OK;
+    };
+    // 1. tile variants, stage by stage, on the first chunk
+    if ((rc = run_field(plan, M, H, 1.0f, s))) { cleanup(); plan->timing_cap = saved_cap; return rc; }
+    const int per = (g.X1 + plan->nch - 1) / plan->nch;
+    for (int st = 0; st < 5 && !rc; ++st) {
+        if ((st == 1 || st == 3) && g.ny == 1) continue;
+        double best = 1e30;
+        int best_v = plan->variant[st];
+        for (int v = 0; v < NVARIANTS && !rc; ++v) {
+            plan->variant[st] = v;
+            StageArgs a = stage_args(plan, s);
+            const int nk = g.ny == 1 ? g.X1 : per;
+            auto fn = [&]() -> int {
+                switch (st) {
+                    case 0: return launch_x_forward(a, M, 1.0f);
+                    case 1: return launch_y_forward(a, 0, nk);
+                    case 2: return launch_z_convolve(a, 0, nk);
+                    case 3: return launch_y_inverse(a, 0, nk);
+                    default: return launch_x_inverse(a, H);
+                }
+            };
+            double ms = 0.0;
+            rc = time_it(fn, 5, &ms);
+            if (!rc && ms < best) {
+                best = ms;
+                best_v = v;
+            }
+        }
+        plan->variant[st] = best_v;
+    }
+    // 2. number of chunks, timing the whole evaluation
+    if (!rc && g.ny > 1) {
+        const int nmin = (g.X1 + plan->xc - 1) / plan->xc;
+        double best = 1e30;
+        int best_n = plan->nch;
+        for (int n = nmin; n <= 8 * nmin && n <= g.X1 && !rc; n *= 2) {
+            plan->nch = n;
+            double ms = 0.0;
+            rc = time_it([&]() { return run_field(plan, M, H, 1.0f, s); }, 3, &ms);
+            if (!rc && ms < best) {
+                best = ms;
+                best_n = n;
+            }
+        }
+        plan->nch = best_n;
+    }
+    plan->timing_cap = saved_cap;
+    cleanup();
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    Tuned t;
+    for (int i = 0; i < 5; ++i) t.variant[i] = plan->variant[i];
+    t.nch = plan->nch;
+    g_tuned[{g.nx, g.ny, g.nz}] = t;
+    return DEMAG_OK;
 }
 
 int demag_timing_enable(demag_plan* plan, int32_t max_records) {

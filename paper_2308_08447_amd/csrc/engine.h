@@ -43,14 +43,18 @@ struct StageArgs {
     const Geometry* g;
     const float2* tw_all;
     float2* S1;            // [3][nz][X1][ny]
-    float2* S2;            // [3][nz][X1][Ny]; == S1 when ny == 1
+    float2* S2;            // chunk buffer [3][nz][xc][Ny]; == S1 (xc = X1) when ny == 1
     const float* K;        // [6][Z1][X1][Y1]
     hipStream_t stream;
+    int variant[5];        // tile-shape variant per stage (0 .. NVARIANTS-1)
+    int xc;                // kx planes the S2 chunk buffer holds
 };
+constexpr int NVARIANTS = 3;
 int launch_x_forward(const StageArgs& a, const float* M, float scale);
-int launch_y_forward(const StageArgs& a);
-int launch_z_convolve(const StageArgs& a);
-int launch_y_inverse(const StageArgs& a);
+// y / z stages over the kx planes [k0, k0 + nk) (nk <= xc)
+int launch_y_forward(const StageArgs& a, int k0, int nk);
+int launch_z_convolve(const StageArgs& a, int k0, int nk);
+int launch_y_inverse(const StageArgs& a, int k0, int nk);
 int launch_x_inverse(const StageArgs& a, float* H);
 // Largest transform length the twiddle table must hold for this geometry.
 int twiddle_table_length(const Geometry& g);

@@ -19,8 +19,11 @@ namespace dm {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// Device code is compiled with -ffp-contract=off: every fused multiply-add is
+// written out, so the rounding of each line's arithmetic is fixed by the source
+// and does not depend on how a kernel instantiation is unrolled or scheduled.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
@@ -164,6 +167,152 @@ __device__ __forceinline__ void fft_passes(float2* buf, const float2* __restrict
         constexpr int R = radix_of(L, P);
         stockham_pass<L, R, NS, DIR, NLINES, NT, Addr>(buf, tw);
         fft_passes<L, P + 1, NS * R, DIR, NLINES, NT, Addr>(buf, tw);
+    }
+}
+
+// Stockham FFT whose first pass reads its inputs through src(line, i) straight
+// into registers and whose last pass hands its outputs to sink(line, k, v)
+// straight from registers; only the passes in between exchange through LDS
+// (buf, addressed by Addr).  A length-L transform with P passes thus touches LDS
+// 2(P-1) times per element instead of 2P + 2.
+//   HALF_IN  inputs i >= L/2 are zero: the first pass neither reads nor adds them
+//            (the padded transforms of the convolution);
+//   SYNC_IO  src or sink touch buf themselves: barriers separate the first pass's
+//            reads from its writes and the last pass's reads from the sink.
+// Consecutive threads take consecutive butterflies in the first and last passes,
+// so for RowLines a global src/sink is coalesced along the line, for ColLines
+// across lines.
+template <int L, int R, int DIR, int NLINES, int NT, class Addr, bool HALF_IN, bool SYNC_IO,
+          bool TO_LDS, class Src>
+__device__ __forceinline__ void first_pass(float2* buf, Src& src) {
+    constexpr int NB = L / R;
+    constexpr int TOT = NB * NLINES;
+    constexpr int PER = (TOT + NT - 1) / NT;
+    constexpr int RIN = HALF_IN ? R / 2 : R;
+    float2 v[PER][R];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        int b = tid + q * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            int line, j;
+            Addr::template split<NB>(b, line, j);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = r < RIN ? src(line, j + r * NB) : make_float2(0.f, 0.f);
+        }
+    }
+    if constexpr (SYNC_IO) __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        int b = tid + q * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            int line, j;
+            Addr::template split<NB>(b, line, j);
+            dft<R, DIR>(v[q]);
+            if constexpr (TO_LDS) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[Addr::idx(line, j * R + r)] = v[q][r];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int L, int R, int DIR, int NLINES, int NT, class Addr, bool HALF_OUT, bool SYNC_IO,
+          class Sink>
+__device__ __forceinline__ void last_pass(float2* buf, const float2* __restrict__ tw, Sink& sink) {
+    constexpr int NB = L / R;  // == NS of this pass
+    constexpr int TOT = NB * NLINES;
+    constexpr int PER = (TOT + NT - 1) / NT;
+    float2 v[PER][R];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        int b = tid + q * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            int line, j;
+            Addr::template split<NB>(b, line, j);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = buf[Addr::idx(line, j + r * NB)];
+        }
+    }
+    if constexpr (SYNC_IO) __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        int b = tid + q * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            int line, j;
+            Addr::template split<NB>(b, line, j);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = tw[j * r];
+                if constexpr (DIR > 0) w.y = -w.y;
+                v[q][r] = cmul(v[q][r], w);
+            }
+            dft<R, DIR>(v[q]);
+            constexpr int ROUT = HALF_OUT ? R / 2 : R;
+#pragma unroll
+            for (int r = 0; r < ROUT; ++r) sink(line, j + r * NB, v[q][r]);
+        }
+    }
+}
+
+template <int L, int P, int NS, int DIR, int NLINES, int NT, class Addr>
+__device__ __forceinline__ void middle_passes(float2* buf, const float2* __restrict__ tw) {
+    if constexpr (P < npasses(L) - 1) {
+        constexpr int R = radix_of(L, P);
+        stockham_pass<L, R, NS, DIR, NLINES, NT, Addr>(buf, tw);
+        middle_passes<L, P + 1, NS * R, DIR, NLINES, NT, Addr>(buf, tw);
+    }
+}
+
+// L <= 16: the whole transform in registers, src -> DFT -> sink.
+template <int L, int DIR, int NLINES, int NT, class Addr, bool HALF_IN, bool HALF_OUT,
+          bool SYNC_IO, class Src, class Sink>
+__device__ __forceinline__ void single_pass(Src& src, Sink& sink) {
+    constexpr int TOT = NLINES;
+    constexpr int PER = (TOT + NT - 1) / NT;
+    constexpr int RIN = HALF_IN ? L / 2 : L;
+    constexpr int ROUT = HALF_OUT ? L / 2 : L;
+    float2 v[PER][L];
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        int b = tid + q * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            int line, j;
+            Addr::template split<1>(b, line, j);
+#pragma unroll
+            for (int r = 0; r < L; ++r) v[q][r] = r < RIN ? src(line, r) : make_float2(0.f, 0.f);
+        }
+    }
+    if constexpr (SYNC_IO) __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        int b = tid + q * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            int line, j;
+            Addr::template split<1>(b, line, j);
+            dft<L, DIR>(v[q]);
+#pragma unroll
+            for (int r = 0; r < ROUT; ++r) sink(line, r, v[q][r]);
+        }
+    }
+}
+
+template <int L, int DIR, int NLINES, int NT, class Addr, bool HALF_IN, bool HALF_OUT,
+          bool SYNC_IO, class Src, class Sink>
+__device__ __forceinline__ void fft_io(float2* buf, const float2* __restrict__ tw, Src src,
+                                       Sink sink) {
+    constexpr int P = npasses(L);
+    if constexpr (P <= 1) {
+        single_pass<L, DIR, NLINES, NT, Addr, HALF_IN, HALF_OUT, SYNC_IO>(src, sink);
+        return;
+    } else {
+    constexpr int R0 = radix_of(L, 0);
+    first_pass<L, R0, DIR, NLINES, NT, Addr, HALF_IN, SYNC_IO, true>(buf, src);
+    middle_passes<L, 1, R0, DIR, NLINES, NT, Addr>(buf, tw);
+    last_pass<L, radix_of(L, P - 1), DIR, NLINES, NT, Addr, HALF_OUT, SYNC_IO>(buf, tw, sink);
     }
 }
 

@@ -24,40 +24,76 @@ namespace dm {
 
 constexpr int NT = 256;
 
+// Workgroups are dispatched to the 8 XCDs round-robin.  Renumber them so that
+// every XCD works on one contiguous range of tiles: neighbouring tiles, which
+// share cache lines of their partial-line segments (transposed rows, kernel
+// rows), then meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int B) {
+    constexpr int NXCD = 8;
+    int x = b % NXCD, i = b / NXCD;
+    int q = B / NXCD, r = B % NXCD;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// The two rows of a packed pair are adjacent in S1 (y fastest): move them as one
+// 16-byte access when both exist (rows are even then, so the address is aligned).
+__device__ __forceinline__ void store_pair(float2* d, float2 a, float2 b, int left) {
+    if (left >= 2) *reinterpret_cast<float4*>(d) = make_float4(a.x, a.y, b.x, b.y);
+    else if (left == 1) d[0] = a;
+}
+__device__ __forceinline__ void load_pair(const float2* s, float2& a, float2& b, int left) {
+    if (left >= 2) {
+        float4 v = *reinterpret_cast<const float4*>(s);
+        a = make_float2(v.x, v.y);
+        b = make_float2(v.z, v.w);
+    } else {
+        a = left == 1 ? s[0] : make_float2(0.f, 0.f);
+        b = make_float2(0.f, 0.f);
+    }
+}
+
+// Copies n table entries into LDS (issued with the block's data loads; the
+// block's first barrier makes them visible).
+__device__ __forceinline__ void stage_table(float2* dst, const float2* __restrict__ src, int n) {
+    for (int i = threadIdx.x; i < n; i += NT) dst[i] = src[i];
+}
+
 // ============================================================================ x
 // One block: component c, plane z, rows y0 .. y0+TY-1 (TY/2 packed pairs).
+// Forward: each pair z = a + i b is transformed twice (even outputs: DFT of z,
+// odd outputs: DFT of z W_2L^t); the first pass reads the rows straight from M,
+// the last pass leaves the spectrum in LDS in natural order, from where the
+// Hermitian separation writes S1 transposed (consecutive threads, consecutive y).
 template <int L, int TY>
 __global__ __launch_bounds__(NT) void x_forward_kernel(const float* __restrict__ M,
                                                        float2* __restrict__ S1, int ny, int nz,
                                                        float scale,
                                                        const float2* __restrict__ tw_all) {
     constexpr int NP = TY / 2;
-    constexpr int LS = lpad_c(L);
-    constexpr int PER = (NP * L + NT - 1) / NT;
+    constexpr int LS = lpad_c(L) + 1;  // odd stride: the pairs of one frequency hit distinct banks
     __shared__ float2 buf[NP * LS];
-    const float2* twL = tw_all + L;
+    __shared__ float2 twL[L];
     const float2* tw2L = tw_all + 2 * L;
+    stage_table(twL, tw_all + L, L);
     const int tid = threadIdx.x;
-    const int y0 = blockIdx.x * TY, z = blockIdx.y, c = blockIdx.z;
+    const int nyt = (ny + TY - 1) / TY;
+    const int id = xcd_tile(blockIdx.x, gridDim.x);
+    const int y0 = (id % nyt) * TY, z = (id / nyt) % nz, c = id / (nyt * nz);
     const int rows = min(TY, ny - y0);
     const float* src = M + ((size_t)(c * nz + z) * ny + y0) * L;
     float2* dst = S1 + (size_t)(c * nz + z) * (L + 1) * ny + y0;
 
-    float2 zr[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        int e = tid + q * NT;
-        if (e < NP * L) {
-            int p = e / L, t = e - p * L;
-            float a = (2 * p < rows) ? src[(size_t)(2 * p) * L + t] : 0.f;
-            float b = (2 * p + 1 < rows) ? src[(size_t)(2 * p + 1) * L + t] : 0.f;
-            zr[q] = make_float2(a * scale, b * scale);
-            buf[p * LS + lpad(t)] = zr[q];
-        }
-    }
-    __syncthreads();
-    lds_fft<L, -1, NP, NT, RowLines<LS>>(buf, twL);
+    auto pair = [&](int p, int t) {
+        float a = (2 * p < rows) ? src[(size_t)(2 * p) * L + t] : 0.f;
+        float b = (2 * p + 1 < rows) ? src[(size_t)(2 * p + 1) * L + t] : 0.f;
+        return make_float2(a * scale, b * scale);
+    };
+    auto pair_odd = [&](int p, int t) { return cmul(pair(p, t), tw2L[t]); };
+    auto to_lds = [&](int p, int k, float2 v) { buf[p * LS + lpad(k)] = v; };
+    using Rows = RowLines<LS>;
 
+    fft_io<L, -1, NP, NT, Rows, false, false, true>(buf, twL, pair, to_lds);
+    __syncthreads();
     // even frequencies kx = 2m, m = 0..L/2: Z[2m] = E[m], Z[2L-2m] = E[(L-m) mod L]
     for (int it = tid; it < (L / 2 + 1) * NP; it += NT) {
         int p = it % NP, m = it / NP;
@@ -66,21 +102,11 @@ __global__ __launch_bounds__(NT) void x_forward_kernel(const float* __restrict__
         float2 Xa = cscale(cadd(Zk, Zn), 0.5f);
         float2 d = csub(Zk, Zn);
         float2 Xb = make_float2(0.5f * d.y, -0.5f * d.x);
-        size_t o = (size_t)(2 * m) * ny + 2 * p;
-        if (2 * p < rows) dst[o] = Xa;
-        if (2 * p + 1 < rows) dst[o + 1] = Xb;
+        store_pair(dst + (size_t)(2 * m) * ny + 2 * p, Xa, Xb, rows - 2 * p);
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        int e = tid + q * NT;
-        if (e < NP * L) {
-            int p = e / L, t = e - p * L;
-            buf[p * LS + lpad(t)] = cmul(zr[q], tw2L[t]);
-        }
-    }
+    fft_io<L, -1, NP, NT, Rows, false, false, true>(buf, twL, pair_odd, to_lds);
     __syncthreads();
-    lds_fft<L, -1, NP, NT, RowLines<LS>>(buf, twL);
     // odd frequencies kx = 2m+1, m < L/2: Z[2m+1] = O[m], Z[2L-2m-1] = O[L-1-m]
     for (int it = tid; it < (L / 2) * NP; it += NT) {
         int p = it % NP, m = it / NP;
@@ -89,36 +115,41 @@ __global__ __launch_bounds__(NT) void x_forward_kernel(const float* __restrict__
         float2 Xa = cscale(cadd(Zk, Zn), 0.5f);
         float2 d = csub(Zk, Zn);
         float2 Xb = make_float2(0.5f * d.y, -0.5f * d.x);
-        size_t o = (size_t)(2 * m + 1) * ny + 2 * p;
-        if (2 * p < rows) dst[o] = Xa;
-        if (2 * p + 1 < rows) dst[o + 1] = Xb;
+        store_pair(dst + (size_t)(2 * m + 1) * ny + 2 * p, Xa, Xb, rows - 2 * p);
     }
 }
 
+// Inverse: the even (odd) inputs Z[2m] (Z[2m+1]) of the packed pair are gathered
+// from S1 (consecutive threads, consecutive y) into LDS; the inverse of the even
+// part is parked in a second LDS region, and the last pass of the odd part
+// combines z[t] = IE[t] + W_2L^-t IO[t] and stores both rows of H directly.
 template <int L, int TY>
 __global__ __launch_bounds__(NT) void x_inverse_kernel(const float2* __restrict__ S1,
                                                        float* __restrict__ H, int ny, int nz,
                                                        const float2* __restrict__ tw_all) {
     constexpr int NP = TY / 2;
-    constexpr int LS = lpad_c(L);
-    constexpr int PER = (NP * L + NT - 1) / NT;
+    constexpr int LS = lpad_c(L) + 1;  // odd stride: the pairs of one frequency hit distinct banks
     __shared__ float2 buf[NP * LS];
-    const float2* twL = tw_all + L;
-    const float2* tw2L = tw_all + 2 * L;
+    __shared__ float2 ie[NP * LS];
+    __shared__ float2 twL[L];
+    __shared__ float2 tw2L[L];  // first half of the length-2L table
+    stage_table(twL, tw_all + L, L);
+    stage_table(tw2L, tw_all + 2 * L, L);
     const int tid = threadIdx.x;
-    const int y0 = blockIdx.x * TY, z = blockIdx.y, c = blockIdx.z;
+    const int nyt = (ny + TY - 1) / TY;
+    const int id = xcd_tile(blockIdx.x, gridDim.x);
+    const int y0 = (id % nyt) * TY, z = (id / nyt) % nz, c = id / (nyt * nz);
     const int rows = min(TY, ny - y0);
     const float2* src = S1 + (size_t)(c * nz + z) * (L + 1) * ny + y0;
     float* dst = H + ((size_t)(c * nz + z) * ny + y0) * L;
+    using Rows = RowLines<LS>;
 
     // Z[k] = Xa[k] + i Xb[k]; for k > L use Hermitian symmetry X[2L-k] = conj(X[k]).
     // The DC and Nyquist bins of a real row are real: their imaginary parts are dropped.
-    // Even inputs Z[2m] -> line p, slot m.
     for (int it = tid; it < (L / 2 + 1) * NP; it += NT) {
         int p = it % NP, m = it / NP, kx = 2 * m;
-        size_t o = (size_t)kx * ny + 2 * p;
-        float2 Xa = (2 * p < rows) ? src[o] : make_float2(0.f, 0.f);
-        float2 Xb = (2 * p + 1 < rows) ? src[o + 1] : make_float2(0.f, 0.f);
+        float2 Xa, Xb;
+        load_pair(src + (size_t)kx * ny + 2 * p, Xa, Xb, rows - 2 * p);
         if (kx == 0 || kx == L) {
             Xa.y = 0.f;
             Xb.y = 0.f;
@@ -127,38 +158,25 @@ __global__ __launch_bounds__(NT) void x_inverse_kernel(const float2* __restrict_
         if (kx > 0 && kx < L) buf[p * LS + lpad(L - m)] = make_float2(Xa.x + Xb.y, Xb.x - Xa.y);
     }
     __syncthreads();
-    lds_fft<L, +1, NP, NT, RowLines<LS>>(buf, twL);
-    float2 ie[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        int e = tid + q * NT;
-        if (e < NP * L) {
-            int p = e / L, t = e - p * L;
-            ie[q] = buf[p * LS + lpad(t)];
-        }
-    }
+    auto from_lds = [&](int p, int t) { return buf[p * LS + lpad(t)]; };
+    auto park = [&](int p, int t, float2 v) { ie[p * LS + lpad(t)] = v; };
+    fft_io<L, +1, NP, NT, Rows, false, false, true>(buf, twL, from_lds, park);
     __syncthreads();
     // Odd inputs Z[2m+1]: kx = 2m+1 < L direct, and Z[2L-kx] = conj -> slot L-1-m.
     for (int it = tid; it < (L / 2) * NP; it += NT) {
         int p = it % NP, m = it / NP, kx = 2 * m + 1;
-        size_t o = (size_t)kx * ny + 2 * p;
-        float2 Xa = (2 * p < rows) ? src[o] : make_float2(0.f, 0.f);
-        float2 Xb = (2 * p + 1 < rows) ? src[o + 1] : make_float2(0.f, 0.f);
+        float2 Xa, Xb;
+        load_pair(src + (size_t)kx * ny + 2 * p, Xa, Xb, rows - 2 * p);
         buf[p * LS + lpad(m)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
         buf[p * LS + lpad(L - 1 - m)] = make_float2(Xa.x + Xb.y, Xb.x - Xa.y);
     }
     __syncthreads();
-    lds_fft<L, +1, NP, NT, RowLines<LS>>(buf, twL);
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        int e = tid + q * NT;
-        if (e < NP * L) {
-            int p = e / L, t = e - p * L;
-            float2 zz = cadd(ie[q], cmul(cconj(tw2L[t]), buf[p * LS + lpad(t)]));
-            if (2 * p < rows) dst[(size_t)(2 * p) * L + t] = zz.x;
-            if (2 * p + 1 < rows) dst[(size_t)(2 * p + 1) * L + t] = zz.y;
-        }
-    }
+    auto combine = [&](int p, int t, float2 io) {
+        float2 zz = cadd(ie[p * LS + lpad(t)], cmul(cconj(tw2L[t]), io));
+        if (2 * p < rows) dst[(size_t)(2 * p) * L + t] = zz.x;
+        if (2 * p + 1 < rows) dst[(size_t)(2 * p + 1) * L + t] = zz.y;
+    };
+    fft_io<L, +1, NP, NT, Rows, false, false, true>(buf, twL, from_lds, combine);
 }
 
 // nx == 1: no x transform (N_x = 1); S1[c][z][0][y] = M[c][z][y][0]
@@ -174,124 +192,193 @@ __global__ void x_copy_inverse_kernel(const float2* __restrict__ S1, float* __re
 }
 
 // ============================================================================ y
-// One block: LPB lines (consecutive kx) of one (c, z) plane; lines [0, LPB) of
-// LDS hold the even-output halves, [LPB, 2 LPB) the odd-output halves.
+// The y and z stages run over a chunk of kx planes [k0, k0 + nk) whose spectra
+// live in a chunk-sized S2 buffer [3][nz][xc][Ny] (local plane kx - k0).
+// One block: LPB lines (consecutive kx) of one (c, z) plane.  Each line is a
+// length-Ny = 2L transform whose upper L inputs are zero (forward) or whose
+// upper L outputs are dropped (inverse); the first pass reads S1/S2 straight
+// into registers and the last pass stores straight from registers.
 template <int L, int LPB>
 __global__ __launch_bounds__(NT) void y_forward_kernel(const float2* __restrict__ S1,
                                                        float2* __restrict__ S2, int X1, int nz,
+                                                       int k0, int nk, int xc,
                                                        const float2* __restrict__ tw_all) {
-    constexpr int LS = lpad_c(L);
-    __shared__ float2 buf[2 * LPB * LS];
-    const float2* twL = tw_all + L;
-    const float2* tw2L = tw_all + 2 * L;
-    const int tid = threadIdx.x;
-    const int kx0 = blockIdx.x * LPB, z = blockIdx.y, c = blockIdx.z;
-    const size_t plane = (size_t)(c * nz + z) * X1;
-    for (int it = tid; it < LPB * L; it += NT) {
-        int l = it / L, t = it - l * L, kx = kx0 + l;
-        float2 v = (kx < X1) ? S1[(plane + kx) * L + t] : make_float2(0.f, 0.f);
-        buf[l * LS + lpad(t)] = v;
-        buf[(LPB + l) * LS + lpad(t)] = cmul(v, tw2L[t]);
-    }
-    __syncthreads();
-    lds_fft<L, -1, 2 * LPB, NT, RowLines<LS>>(buf, twL);
-    for (int it = tid; it < LPB * L; it += NT) {
-        int l = it / L, m = it - l * L, kx = kx0 + l;
-        if (kx < X1) {
-            float2 e = buf[l * LS + lpad(m)], o = buf[(LPB + l) * LS + lpad(m)];
-            float4* d = reinterpret_cast<float4*>(S2 + (plane + kx) * (2 * L)) + m;
-            *d = make_float4(e.x, e.y, o.x, o.y);
-        }
-    }
+    constexpr int LN = 2 * L;
+    constexpr int LS = lpad_c(LN);
+    __shared__ float2 buf[LPB * LS];
+    __shared__ float2 tw[LN];
+    stage_table(tw, tw_all + LN, LN);
+    const int nt = (nk + LPB - 1) / LPB;
+    const int id = xcd_tile(blockIdx.x, gridDim.x);
+    const int kl0 = (id % nt) * LPB, z = (id / nt) % nz, c = id / (nt * nz);
+    const int nl = nk - kl0 < LPB ? nk - kl0 : LPB;  // valid lines in this block
+    const float2* in = S1 + ((size_t)(c * nz + z) * X1 + k0 + kl0) * L;
+    float2* out = S2 + ((size_t)(c * nz + z) * xc + kl0) * LN;
+    auto src = [&](int l, int i) { return l < nl ? in[(size_t)l * L + i] : make_float2(0.f, 0.f); };
+    auto sink = [&](int l, int k, float2 v) {
+        if (l < nl) out[(size_t)l * LN + k] = v;
+    };
+    fft_io<LN, -1, LPB, NT, RowLines<LS>, true, false, false>(buf, tw, src, sink);
 }
 
 template <int L, int LPB>
 __global__ __launch_bounds__(NT) void y_inverse_kernel(const float2* __restrict__ S2,
                                                        float2* __restrict__ S1, int X1, int nz,
+                                                       int k0, int nk, int xc,
                                                        const float2* __restrict__ tw_all) {
-    constexpr int LS = lpad_c(L);
-    __shared__ float2 buf[2 * LPB * LS];
-    const float2* twL = tw_all + L;
-    const float2* tw2L = tw_all + 2 * L;
-    const int tid = threadIdx.x;
-    const int kx0 = blockIdx.x * LPB, z = blockIdx.y, c = blockIdx.z;
-    const size_t plane = (size_t)(c * nz + z) * X1;
-    for (int it = tid; it < LPB * L; it += NT) {
-        int l = it / L, m = it - l * L, kx = kx0 + l;
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (kx < X1) v = reinterpret_cast<const float4*>(S2 + (plane + kx) * (2 * L))[m];
-        buf[l * LS + lpad(m)] = make_float2(v.x, v.y);
-        buf[(LPB + l) * LS + lpad(m)] = make_float2(v.z, v.w);
-    }
-    __syncthreads();
-    lds_fft<L, +1, 2 * LPB, NT, RowLines<LS>>(buf, twL);
-    for (int it = tid; it < LPB * L; it += NT) {
-        int l = it / L, t = it - l * L, kx = kx0 + l;
-        if (kx < X1) {
-            float2 e = buf[l * LS + lpad(t)], o = buf[(LPB + l) * LS + lpad(t)];
-            S1[(plane + kx) * L + t] = cadd(e, cmul(cconj(tw2L[t]), o));
-        }
-    }
+    constexpr int LN = 2 * L;
+    constexpr int LS = lpad_c(LN);
+    __shared__ float2 buf[LPB * LS];
+    __shared__ float2 tw[LN];
+    stage_table(tw, tw_all + LN, LN);
+    const int nt = (nk + LPB - 1) / LPB;
+    const int id = xcd_tile(blockIdx.x, gridDim.x);
+    const int kl0 = (id % nt) * LPB, z = (id / nt) % nz, c = id / (nt * nz);
+    const int nl = nk - kl0 < LPB ? nk - kl0 : LPB;
+    const float2* in = S2 + ((size_t)(c * nz + z) * xc + kl0) * LN;
+    float2* out = S1 + ((size_t)(c * nz + z) * X1 + k0 + kl0) * L;
+    auto src = [&](int l, int i) { return l < nl ? in[(size_t)l * LN + i] : make_float2(0.f, 0.f); };
+    auto sink = [&](int l, int k, float2 v) {
+        if (l < nl) out[(size_t)l * L + k] = v;
+    };
+    fft_io<LN, +1, LPB, NT, RowLines<LS>, false, true, false>(buf, tw, src, sink);
 }
 
 // ============================================================================ z
-// One block: TK consecutive ky of one kx, all stored z planes, 3 components.
-// LDS element (z, c, t) at z * 3TK + c * TK + t: 3TK interleaved lines of length NZ.
-template <int NZ, int TK>
+// One block: folded ky indices f in [f0, f0 + th) of one kx, each taken together
+// with its mirror ky = Ny - f, so that the kernel values K(kx, |ky|, |kz|) are read
+// once for both.  The mirror slot of f = 0 (which has no mirror) carries the
+// Nyquist column ky = Ny/2 instead.  Column j < TH holds ky = f0 + j, column
+// TH + j holds the mirror of f0 + j.  All stored z planes of the 3 components are
+// loaded into registers together with the K tile (so every global load of the
+// block is in flight at once), then staged in LDS: element (z, c, column) at
+// z * 3NC + c * NC + column, i.e. 3NC interleaved lines of length NZ.
+template <int NZ, int TH>
 __global__ __launch_bounds__(NT) void z_convolve_kernel(float2* __restrict__ S2,
-                                                        const float* __restrict__ K, int nz,
-                                                        int X1, int Ny, int Y1, int Z1,
+                                                        const float* __restrict__ K, int X1,
+                                                        int Ny, int Y1, int Z1, int k0, int xc,
                                                         const float2* __restrict__ tw_all) {
-    constexpr int NLN = 3 * TK;
+    constexpr int NZH = NZ > 1 ? NZ / 2 : 1;   // stored z planes
+    constexpr int KT = NZ > 1 ? NZ / 2 + 1 : 1;  // folded kz values
+    constexpr int NC = 2 * TH;                   // columns per block
+    constexpr int NLN = 3 * NC;
     __shared__ float2 buf[NZ * NLN];
-    const float2* twZ = tw_all + NZ;
+    __shared__ float ks[6 * KT * (TH + 1)];      // [comp][kz][f - f0], slot TH = Nyquist
+    __shared__ float2 twZ[NZ];
+    stage_table(twZ, tw_all + NZ, NZ);
     const int tid = threadIdx.x;
-    const int ky0 = blockIdx.x * TK, kx = blockIdx.y;
-    const size_t P = (size_t)X1 * Ny;  // complex elements per z plane
-    const size_t cstride = (size_t)nz * P;
-    float2* col = S2 + (size_t)kx * Ny + ky0;
+    const int ny = Ny > 1 ? Ny / 2 : 1;
+    const int th = TH < ny ? TH : ny;
+    const int nft = ny / th;
+    const int id = xcd_tile(blockIdx.x, gridDim.x);
+    const int f0 = (id % nft) * th, kl = id / nft, kx = k0 + kl;
+    const size_t P = (size_t)xc * Ny;  // complex elements per z plane of the chunk
+    const size_t cstride = (size_t)NZH * P;
+    float2* col = S2 + (size_t)kl * Ny;
+    const bool nyq = (f0 == 0 && Ny > 1);
+    auto col_ky = [&](int j) -> int {
+        if (j < TH) return j < th ? f0 + j : -1;
+        int jj = j - TH;
+        if (jj >= th) return -1;
+        int f = f0 + jj;
+        if (f == 0) return nyq ? Ny / 2 : -1;
+        return Ny - f;
+    };
 
-    for (int it = tid; it < 3 * NZ * TK; it += NT) {
-        int t = it % TK, rest = it / TK, zz = rest % NZ, c = rest / NZ;
-        float2 v = make_float2(0.f, 0.f);
-        if (zz < nz && ky0 + t < Ny) v = col[c * cstride + zz * P + t];
-        buf[zz * NLN + c * TK + t] = v;
+    // kernel tile: slot j < TH holds folded ky = f0 + j, slot TH the Nyquist column
+    constexpr int NKL = 6 * KT * (TH + 1);
+    constexpr int PK = (NKL + NT - 1) / NT;
+    float kr[PK];
+#pragma unroll
+    for (int q = 0; q < PK; ++q) {
+        int it = tid + q * NT;
+        kr[q] = 0.f;
+        if (it < NKL) {
+            int j = it % (TH + 1), rest = it / (TH + 1), kz = rest % KT, comp = rest / KT;
+            int f = (j < TH) ? (j < th ? f0 + j : -1) : (nyq ? Ny / 2 : -1);
+            if (f >= 0) kr[q] = K[(((size_t)comp * Z1 + kz) * X1 + kx) * Y1 + f];
+        }
+    }
+    // LDS line (c, column) = c * NC + column; element z of a line at z * NLN + line
+    auto gsrc = [&](int line, int zz) {
+        int c = line / NC, j = line - c * NC;
+        int ky = col_ky(j);
+        return ky >= 0 ? col[c * cstride + zz * P + ky] : make_float2(0.f, 0.f);
+    };
+    auto lds_sink = [&](int line, int k, float2 v) { buf[k * NLN + line] = v; };
+    if constexpr (NZ == 1) {
+        for (int line = tid; line < NLN; line += NT) buf[line] = gsrc(line, 0);
+    } else {
+        fft_io<NZ, -1, NLN, NT, ColLines<NLN>, true, false, true>(buf, twZ, gsrc, lds_sink);
+    }
+    // the kernel tile goes to LDS only now, so its loads overlapped the transform
+#pragma unroll
+    for (int q = 0; q < PK; ++q) {
+        int it = tid + q * NT;
+        if (it < NKL) ks[it] = kr[q];
     }
     __syncthreads();
-    lds_fft<NZ, -1, NLN, NT, ColLines<NLN>>(buf, twZ);
 
-    const size_t kc = (size_t)Z1 * X1 * Y1;  // floats per K component
-    for (int it = tid; it < NZ * TK; it += NT) {
-        int t = it % TK, kz = it / TK, ky = ky0 + t;
-        if (ky >= Ny) continue;
-        int kyf = ky, kzf = kz;
-        float sy = 1.f, sz = 1.f;
-        if (2 * ky > Ny) { kyf = Ny - ky; sy = -1.f; }
+    for (int it = tid; it < NZ * NC; it += NT) {
+        int j = it % NC, kz = it / NC;
+        if (col_ky(j) < 0) continue;
+        int kzf = kz;
+        float sz = 1.f;
         if (2 * kz > NZ) { kzf = NZ - kz; sz = -1.f; }
-        const float* k0 = K + ((size_t)kzf * X1 + kx) * Y1 + kyf;
-        float kxx = k0[0], kyy = k0[kc], kzz = k0[2 * kc];
-        float kxy = sy * k0[3 * kc], kxz = sz * k0[4 * kc], kyz = sy * sz * k0[5 * kc];
-        float2* p = buf + kz * NLN + t;
-        float2 mx = p[0], my = p[TK], mz = p[2 * TK];
-        p[0] = make_float2(kxx * mx.x + kxy * my.x + kxz * mz.x, kxx * mx.y + kxy * my.y + kxz * mz.y);
-        p[TK] = make_float2(kxy * mx.x + kyy * my.x + kyz * mz.x, kxy * mx.y + kyy * my.y + kyz * mz.y);
-        p[2 * TK] = make_float2(kxz * mx.x + kyz * my.x + kzz * mz.x, kxz * mx.y + kyz * my.y + kzz * mz.y);
+        int jj = j < TH ? j : j - TH;
+        float sy = 1.f;
+        int slot = jj;
+        if (j >= TH) {
+            if (f0 + jj == 0) slot = TH;   // Nyquist column, folded index Ny/2
+            else sy = -1.f;
+        }
+        const float* k0p = ks + kzf * (TH + 1) + slot;
+        constexpr int KC = KT * (TH + 1);
+        float kxx = k0p[0], kyy = k0p[KC], kzz = k0p[2 * KC];
+        float kxy = sy * k0p[3 * KC], kxz = sz * k0p[4 * KC], kyz = sy * sz * k0p[5 * KC];
+        float2* p = buf + kz * NLN + j;
+        float2 mx = p[0], my = p[NC], mz = p[2 * NC];
+        auto dot3 = [](float a, float x, float b, float y, float c, float z) {
+            return fmaf(c, z, fmaf(b, y, a * x));
+        };
+        p[0] = make_float2(dot3(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3(kxx, mx.y, kxy, my.y, kxz, mz.y));
+        p[NC] = make_float2(dot3(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3(kxy, mx.y, kyy, my.y, kyz, mz.y));
+        p[2 * NC] = make_float2(dot3(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3(kxz, mx.y, kyz, my.y, kzz, mz.y));
     }
     __syncthreads();
-    lds_fft<NZ, +1, NLN, NT, ColLines<NLN>>(buf, twZ);
 
-    for (int it = tid; it < 3 * nz * TK; it += NT) {
-        int t = it % TK, rest = it / TK, zz = rest % nz, c = rest / nz;
-        if (ky0 + t < Ny) col[c * cstride + zz * P + t] = buf[zz * NLN + c * TK + t];
+    auto lds_src = [&](int line, int zz) { return buf[zz * NLN + line]; };
+    auto gsink = [&](int line, int zz, float2 v) {
+        int c = line / NC, j = line - c * NC;
+        int ky = col_ky(j);
+        if (ky >= 0) col[c * cstride + zz * P + ky] = v;
+    };
+    if constexpr (NZ == 1) {
+        for (int line = tid; line < NLN; line += NT) gsink(line, 0, buf[line]);
+    } else {
+        fft_io<NZ, +1, NLN, NT, ColLines<NLN>, false, true, true>(buf, twZ, lds_src, gsink);
     }
 }
 
 // ============================================================================ launchers
+// Each stage has NVARIANTS tile shapes (more rows/lines/columns per block as the
+// variant index grows); every variant computes bit-identical results because
+// the per-line arithmetic does not depend on how many lines share a block.
 namespace {
 
-constexpr int x_rows(int L) { return L >= 2048 ? 8 : 16; }
-constexpr int y_lines(int L) { return L >= 2048 ? 1 : 2048 / L; }
-constexpr int z_tile(int NZ) { return NZ >= 128 ? 16 : (2048 / NZ > 64 ? 64 : 2048 / NZ); }
+// x: rows per block (TY) = 4, 8, 16, capped so a block's LDS stays modest for
+// long rows (the inverse holds two row buffers)
+template <int L, int V, bool INV>
+struct XTile {
+    static constexpr int CAP = (INV ? 8192 : 16384) / L < 2 ? 2 : (INV ? 8192 : 16384) / L;
+    static constexpr int TY = (4 << V) < CAP ? (4 << V) : CAP;
+};
+// y: padded elements per block 1024, 2048, 4096 -> lines per block
+template <int L, int V>
+struct YTile { static constexpr int LPB = 2 * L >= (1024 << V) ? 1 : (1024 << V) / (2 * L); };
+// z: NZ * TH = 256, 512, 1024
+template <int NZ, int V>
+struct ZTile { static constexpr int TH = (256 << V) / NZ < 1 ? 1 : (256 << V) / NZ; };
 
 }  // namespace
 
@@ -299,8 +386,16 @@ constexpr int z_tile(int NZ) { return NZ >= 128 ? 16 : (2048 / NZ > 64 ? 64 : 20
     MACRO(2) MACRO(4) MACRO(8) MACRO(16) MACRO(32) MACRO(64) MACRO(128) MACRO(256) MACRO(512) \
     MACRO(1024) MACRO(2048)
 
+#define DM_VARIANTS(BODY) \
+    switch (variant) {    \
+        case 0: BODY(0) break; \
+        case 1: BODY(1) break; \
+        default: BODY(2) break; \
+    }
+
 int launch_x_forward(const StageArgs& a, const float* M, float scale) {
     const Geometry& g = *a.g;
+    const int variant = a.variant[0];
     if (g.nx == 1) {
         size_t n = (size_t)3 * g.nz * g.ny;
         hipLaunchKernelGGL(x_copy_forward_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
@@ -309,16 +404,22 @@ int launch_x_forward(const StageArgs& a, const float* M, float scale) {
         return DEMAG_OK;
     }
     switch (g.nx) {
-#define CASE(L)                                                                              \
-    case L: {                                                                                \
-        constexpr int TY = x_rows(L);                                                        \
-        dim3 grid((g.ny + TY - 1) / TY, g.nz, 3);                                            \
-        hipLaunchKernelGGL((x_forward_kernel<L, TY>), grid, dim3(NT), 0, a.stream, M, a.S1, \
-                           g.ny, g.nz, scale, a.tw_all);                                     \
-        break;                                                                               \
+#define BODY(V)                                                                               \
+    {                                                                                         \
+        constexpr int TY = XTile<L, V, false>::TY;                                            \
+        dim3 grid((unsigned)(((g.ny + TY - 1) / TY) * g.nz * 3));                            \
+        hipLaunchKernelGGL((x_forward_kernel<L, TY>), grid, dim3(NT), 0, a.stream, M, a.S1,  \
+                           g.ny, g.nz, scale, a.tw_all);                                      \
+    }
+#define CASE(Lv)                    \
+    case Lv: {                      \
+        constexpr int L = Lv;       \
+        DM_VARIANTS(BODY)           \
+        break;                      \
     }
         DM_POW2_CASES(CASE)
 #undef CASE
+#undef BODY
         default: return fail(DEMAG_EUNSUPPORTED, "x stage: unsupported nx");
     }
     DM_CHECK_LAUNCH();
@@ -327,6 +428,7 @@ int launch_x_forward(const StageArgs& a, const float* M, float scale) {
 
 int launch_x_inverse(const StageArgs& a, float* H) {
     const Geometry& g = *a.g;
+    const int variant = a.variant[4];
     if (g.nx == 1) {
         size_t n = (size_t)3 * g.nz * g.ny;
         hipLaunchKernelGGL(x_copy_inverse_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
@@ -335,75 +437,103 @@ int launch_x_inverse(const StageArgs& a, float* H) {
         return DEMAG_OK;
     }
     switch (g.nx) {
-#define CASE(L)                                                                              \
-    case L: {                                                                                \
-        constexpr int TY = x_rows(L);                                                        \
-        dim3 grid((g.ny + TY - 1) / TY, g.nz, 3);                                            \
-        hipLaunchKernelGGL((x_inverse_kernel<L, TY>), grid, dim3(NT), 0, a.stream, a.S1, H, \
-                           g.ny, g.nz, a.tw_all);                                            \
-        break;                                                                               \
+#define BODY(V)                                                                               \
+    {                                                                                         \
+        constexpr int TY = XTile<L, V, true>::TY;                                             \
+        dim3 grid((unsigned)(((g.ny + TY - 1) / TY) * g.nz * 3));                            \
+        hipLaunchKernelGGL((x_inverse_kernel<L, TY>), grid, dim3(NT), 0, a.stream, a.S1, H,  \
+                           g.ny, g.nz, a.tw_all);                                             \
+    }
+#define CASE(Lv)                    \
+    case Lv: {                      \
+        constexpr int L = Lv;       \
+        DM_VARIANTS(BODY)           \
+        break;                      \
     }
         DM_POW2_CASES(CASE)
 #undef CASE
+#undef BODY
         default: return fail(DEMAG_EUNSUPPORTED, "x stage: unsupported nx");
     }
     DM_CHECK_LAUNCH();
     return DEMAG_OK;
 }
 
-int launch_y_forward(const StageArgs& a) {
+int launch_y_forward(const StageArgs& a, int k0, int nk) {
     const Geometry& g = *a.g;
+    const int variant = a.variant[1];
     if (g.ny == 1) return DEMAG_OK;  // S2 aliases S1
     switch (g.ny) {
-#define CASE(L)                                                                                \
-    case L: {                                                                                  \
-        constexpr int LPB = y_lines(L);                                                        \
-        dim3 grid((g.X1 + LPB - 1) / LPB, g.nz, 3);                                            \
+#define BODY(V)                                                                                 \
+    {                                                                                           \
+        constexpr int LPB = YTile<L, V>::LPB;                                                   \
+        dim3 grid((unsigned)(((nk + LPB - 1) / LPB) * g.nz * 3));                              \
         hipLaunchKernelGGL((y_forward_kernel<L, LPB>), grid, dim3(NT), 0, a.stream, a.S1, a.S2, \
-                           g.X1, g.nz, a.tw_all);                                              \
-        break;                                                                                 \
+                           g.X1, g.nz, k0, nk, a.xc, a.tw_all);                                 \
+    }
+#define CASE(Lv)                    \
+    case Lv: {                      \
+        constexpr int L = Lv;       \
+        DM_VARIANTS(BODY)           \
+        break;                      \
     }
         DM_POW2_CASES(CASE)
 #undef CASE
+#undef BODY
         default: return fail(DEMAG_EUNSUPPORTED, "y stage: unsupported ny");
     }
     DM_CHECK_LAUNCH();
     return DEMAG_OK;
 }
 
-int launch_y_inverse(const StageArgs& a) {
+int launch_y_inverse(const StageArgs& a, int k0, int nk) {
     const Geometry& g = *a.g;
+    const int variant = a.variant[3];
     if (g.ny == 1) return DEMAG_OK;
     switch (g.ny) {
-#define CASE(L)                                                                                \
-    case L: {                                                                                  \
-        constexpr int LPB = y_lines(L);                                                        \
-        dim3 grid((g.X1 + LPB - 1) / LPB, g.nz, 3);                                            \
+#define BODY(V)                                                                                 \
+    {                                                                                           \
+        constexpr int LPB = YTile<L, V>::LPB;                                                   \
+        dim3 grid((unsigned)(((nk + LPB - 1) / LPB) * g.nz * 3));                              \
         hipLaunchKernelGGL((y_inverse_kernel<L, LPB>), grid, dim3(NT), 0, a.stream, a.S2, a.S1, \
-                           g.X1, g.nz, a.tw_all);                                              \
-        break;                                                                                 \
+                           g.X1, g.nz, k0, nk, a.xc, a.tw_all);                                 \
+    }
+#define CASE(Lv)                    \
+    case Lv: {                      \
+        constexpr int L = Lv;       \
+        DM_VARIANTS(BODY)           \
+        break;                      \
     }
         DM_POW2_CASES(CASE)
 #undef CASE
+#undef BODY
         default: return fail(DEMAG_EUNSUPPORTED, "y stage: unsupported ny");
     }
     DM_CHECK_LAUNCH();
     return DEMAG_OK;
 }
 
-int launch_z_convolve(const StageArgs& a) {
+int launch_z_convolve(const StageArgs& a, int k0, int nk) {
     const Geometry& g = *a.g;
+    const int variant = a.variant[2];
     switch (g.Nz) {
-#define CASE(NZv)                                                                             \
-    case NZv: {                                                                               \
-        constexpr int TK = z_tile(NZv);                                                       \
-        dim3 grid((g.Ny + TK - 1) / TK, g.X1);                                                \
-        hipLaunchKernelGGL((z_convolve_kernel<NZv, TK>), grid, dim3(NT), 0, a.stream, a.S2, a.K, \
-                           g.nz, g.X1, g.Ny, g.Y1, g.Z1, a.tw_all);                           \
-        break;                                                                                \
+#define BODY(V)                                                                                \
+    {                                                                                          \
+        constexpr int TH = ZTile<NZ, V>::TH;                                                   \
+        int th = TH < g.ny ? TH : g.ny;                                                        \
+        dim3 grid((unsigned)((g.ny / th) * nk));                                               \
+        hipLaunchKernelGGL((z_convolve_kernel<NZ, TH>), grid, dim3(NT), 0, a.stream, a.S2, a.K, \
+                           g.X1, g.Ny, g.Y1, g.Z1, k0, a.xc, a.tw_all);                        \
+    }
+#define CASE(NZv)                   \
+    case NZv: {                     \
+        constexpr int NZ = NZv;     \
+        DM_VARIANTS(BODY)           \
+        break;                      \
     }
         CASE(1) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64) CASE(128) CASE(256)
 #undef CASE
+#undef BODY
         default: return fail(DEMAG_EUNSUPPORTED, "z stage: unsupported nz");
     }
     DM_CHECK_LAUNCH();

@@ -218,7 +218,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
             for (int u = 0; u < 4; ++u) a[u] = As[rr][ty + 16 * u];
             for (int v = 0; v < 4; ++v) bb[v] = Bs[rr][tx + 16 * v];
             for (int u = 0; u < 4; ++u)
-                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * bb[v];
+                for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], bb[v], acc[u][v]);
         }
         __syncthreads();
     }

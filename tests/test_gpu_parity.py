@@ -150,6 +150,48 @@ def test_field_is_deterministic(gpu_lib, torch_dev):
         pkg.demag_destroy(plan)
 
 
+@pytest.mark.parametrize("n", [(64, 32, 8), (32, 64, 1), (16, 8, 32), (128, 4, 2), (16, 1, 8)],
+                         ids=lambda n: "x".join(map(str, n)))
+def test_variants_are_bit_identical(gpu_lib, torch_dev, n):
+    """Every tile-shape variant of every stage, and the autotuned choice, give the
+    same bits (the per-line arithmetic does not depend on the tile shape)."""
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    _say("variants", n)
+    plan = pkg.demag_setup(n + W.CELL_4NM)
+    try:
+        M = torch.from_numpy(W.magnetisation(n, 8)).cuda()
+        ref = torch.empty_like(M)
+        pkg.demag_field(plan, M, ref)
+        for v in range(pkg.NVARIANTS):
+            for st in range(5):
+                pkg.demag_set_variant(plan, st, v)
+            H = torch.empty_like(M)
+            pkg.demag_field(plan, M, H)
+            torch.cuda.synchronize()
+            assert torch.equal(H, ref), v
+        for v in range(pkg.NVARIANTS):
+            for st in range(5):
+                pkg.demag_set_variant(plan, st, v)
+            for nch in (1, 2, 3, 7):
+                pkg.demag_set_chunks(plan, nch)
+                H = torch.empty_like(M)
+                pkg.demag_field(plan, M, H)
+                torch.cuda.synchronize()
+                assert torch.equal(H, ref), (v, nch)
+        pkg.demag_autotune(plan)
+        chosen = [pkg.demag_get_variant(plan, st) for st in range(5)]
+        _say("  autotuned variants", chosen, "chunks", pkg.demag_get_chunks(plan))
+        H = torch.empty_like(M)
+        pkg.demag_field(plan, M, H)
+        torch.cuda.synchronize()
+        assert torch.equal(H, ref)
+        Href = odemag.demag_fft(M.cpu().numpy().astype(np.float64), W.CELL_4NM)
+        assert max(odemag.rel_l2_per_field(ref.cpu().numpy(), Href)) <= TOL
+    finally:
+        pkg.demag_destroy(plan)
+
+
 def test_abi_rejects_bad_arguments(gpu_lib, torch_dev):
     import paper_2308_08447_amd as pkg
     torch = torch_dev
