@@ -76,12 +76,193 @@ def cpu_baseline(n, cell, budget_s=20.0):
                       f"median {t:.3f} s each"}
 
 
+def serve_run(pkg, reqs, rate, budget, max_active, flags):
+    """Runs one request mix through the server.  rate None = all submitted at
+    once (closed loop); else Poisson arrivals of that rate (1/s).  Returns
+    (wall seconds, latencies, stats)."""
+    import threading
+    import workloads as W
+    srv = pkg.serve_open(budget, max_active, flags)
+    ids = [None] * len(reqs)
+    arrivals = (W.poisson_arrivals(len(reqs), rate, seed=17) if rate else np.zeros(len(reqs)))
+    t0 = time.perf_counter()
+
+    def submitter():
+        for i, (n, alpha, steps, m0) in enumerate(reqs):
+            wait = t0 + arrivals[i] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            ids[i] = pkg.serve_submit(srv, n + W.CELL_4NM, (W.MS, W.A_EX, alpha, 2.21276e5,
+                                                            (0.0, 0.0, 0.0)), 1e-13, steps, m0)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat = []
+    try:
+        for i, (n, alpha, steps, m0) in enumerate(reqs):
+            while ids[i] is None:
+                time.sleep(1e-4)
+            lat.append(pkg.serve_wait(srv, ids[i], np.empty_like(m0)))
+        th.join()
+        wall = time.perf_counter() - t0
+        stats = pkg.serve_get_stats(srv)
+    finally:
+        pkg.serve_close(srv)
+    return wall, np.array(lat), stats
+
+
+def serve_bench(pkg, count, steps, loads, budget=16 << 30, max_active=64, seed=2024):
+    """Serving workload: `count` independent LLG relaxations, meshes drawn
+    uniformly from {32..512}^2 x {1,2,4,8} (4 nm cells), alpha ~ U[0.01, 0.5],
+    seeded random m, RK4 dt = 1e-13 s, `steps` steps each, HBM budget 16 GB."""
+    import workloads as W
+    mix = W.serve_requests(count, seed)
+    reqs = [(n, a, steps, W.unit_vectors((n[2], n[1], n[0]), s % 1000003)) for n, a, s in mix]
+    flags = pkg.SERVE_GRAPHS
+    # closed loop (everything queued at t = 0): saturated throughput
+    wall, lat, st = serve_run(pkg, reqs, None, budget, max_active, flags)
+    thr = count / wall
+    out = {"requests": count, "steps_per_request": steps, "hbm_budget_GB": budget / 2**30,
+           "max_active": max_active, "closed_loop_req_per_s": round(thr, 3),
+           "closed_loop_cell_steps_per_s": round(st["cell_steps"] / wall, 1),
+           "peak_GB": round(st["peak_bytes"] / 2**30, 2), "graph_captures": st["graph_captures"],
+           "open_loop": []}
+    for f in loads:
+        wall, lat, st = serve_run(pkg, reqs, f * thr, budget, max_active, flags)
+        out["open_loop"].append({"load": f, "arrival_rate_per_s": round(f * thr, 3),
+                                 "p50_s": round(float(np.percentile(lat, 50)), 4),
+                                 "p99_s": round(float(np.percentile(lat, 99)), 4),
+                                 "req_per_s": round(count / wall, 3),
+                                 "cell_steps_per_s": round(st["cell_steps"] / wall, 1)})
+    return out
+
+
+def _stage_table(nbytes, stages, evals):
+    per_stage = {}
+    for name, (tot_ms, cnt) in stages.items():
+        if cnt:
+            per_launch = nbytes[name] * evals / cnt
+            avg = tot_ms / cnt
+            per_stage[name] = {"avg_us": round(1e3 * avg, 2), "launches": cnt,
+                               "bytes_per_launch": int(per_launch),
+                               "GB_per_s": round(per_launch / (avg * 1e-3) / 1e9, 1),
+                               "us_per_eval": round(1e3 * tot_ms / evals, 2)}
+    return per_stage
+
+
+def large_film_bench(pkg, args):
+    """demag_field on 1024x1024x32 cells of 4 nm, seeded random unit M x Ms."""
+    import torch
+    import workloads as W
+    cfg = W.LARGE_FILM
+    n, cell = cfg["n"], cfg["cell"]
+    cells = n[0] * n[1] * n[2]
+    stream = torch.cuda.current_stream()
+    plan = pkg.demag_setup(n + cell, stream=stream)
+    pkg.demag_autotune(plan, stream)
+    nch = pkg.demag_get_chunks(plan)
+    M = torch.from_numpy(W.magnetisation(n, 0)).cuda()
+    H = torch.empty_like(M)
+    for _ in range(args.warmup):
+        pkg.demag_field(plan, M, H, stream)
+    torch.cuda.synchronize()
+    pkg.demag_timing_enable(plan, args.steps * nch)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pkg.demag_field(plan, M, H, stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stages = pkg.demag_timing_read(plan)
+    pkg.demag_timing_enable(plan, 0)
+    # untimed: the same field without events, and a sampled check against the oracle
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        pkg.demag_field(plan, M, H, stream)
+    torch.cuda.synchronize()
+    t_field = (time.perf_counter() - t1) / args.steps
+    Hh = H.cpu().numpy()
+    pkg.demag_destroy(plan)
+    nbytes = stage_bytes(n)
+    per_stage = _stage_table(nbytes, stages, args.steps)
+    dom = max(per_stage, key=lambda k: per_stage[k]["avg_us"] * per_stage[k]["launches"])
+    b5 = sum(v for k, v in nbytes.items() if k != "llg")
+    out = {"metric": "demag H_d evals: Gcells/s + % HBM roofline", "value": round(cells / t_field / 1e9, 3),
+           "unit": "Gcells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1e3 * t_field, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": cfg["name"], "mesh": list(n), "yz_chunks": nch},
+           "roofline": {"bound": "hbm", "kernel": dom, "achieved": per_stage[dom]["GB_per_s"],
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(per_stage[dom]["GB_per_s"] / HBM_PEAK_GBS, 4), "traffic": None},
+           "stages": per_stage, "demag_field_effective_frac": round(b5 / t_field / 1e9 / HBM_PEAK_GBS, 4),
+           "timed_with_events_ms": round(1e3 * el / args.steps, 4)}
+    if not args.no_cpu_baseline:
+        # sampled parity: H at a few cells by the oracle's direct sum (all sources)
+        from oracle import demag as odemag
+        Mh = M.cpu().numpy().astype(np.float64)
+        rng = np.random.default_rng(3)
+        tg = np.stack([rng.integers(0, n[0], 3), rng.integers(0, n[1], 3), rng.integers(0, n[2], 3)], 1)
+        t2 = time.perf_counter()
+        ref = odemag.demag_at(Mh, cell, tg)
+        t_or = time.perf_counter() - t2
+        got = np.stack([Hh[:, z, y, x] for x, y, z in tg], 1)
+        out["sampled_parity"] = {"cells": tg.tolist(),
+                                 "max_rel_err": float(np.abs(got - ref).max() / np.abs(ref).max())}
+        out["cpu_baseline"] = {"value": len(tg) / t_or / 1e9, "unit": "Gcells/s", "cores": 1,
+                               "kind": "oracle", "sample": f"direct sum at {len(tg)} cells "
+                               f"(all {cells} sources each), {t_or:.1f} s"}
+    return out
+
+
+def atomistic_bench(pkg, args):
+    """Heun steps of 1024x1024x256 spins (a = 0.4 nm, J = 1e-21 J, mu_s = 1 muB,
+    alpha = 0.05, dt = 1e-15 s, T = 0), demag on 4^3-spin macrocells."""
+    import torch
+    import workloads as W
+    cfg = W.ATOMISTIC
+    n = cfg["n"]
+    spins = n[0] * n[1] * n[2]
+    stream = torch.cuda.current_stream()
+    plan = pkg.atom_setup((n[0], n[1], n[2], cfg["a"], cfg["macro"]), stream=stream)
+    S = torch.from_numpy(W.unit_vectors((n[2], n[1], n[0]), seed=0)).cuda()
+    prm = (cfg["J"], cfg["mu_s"], cfg["alpha"], 2.21276e5, (0.0, 0.0, 0.0))
+    pkg.atom_step(plan, S, prm, cfg["dt"], args.warmup, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pkg.atom_step(plan, S, prm, cfg["dt"], args.steps, stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    pkg.atom_destroy(plan)
+    norm_err = float((S.norm(dim=0) - 1).abs().max())
+    # Heun step bytes: 2 macro averages (12 B/spin each), predictor (read 12, write 24),
+    # corrector (read 36, write 12); neighbour re-reads come from cache
+    per_spin = 2 * 12 + 36 + 48
+    ms = 1e3 * el / args.steps
+    return {"metric": "atomistic spin-steps/s", "value": round(spins * args.steps / el / 1e9, 3),
+            "unit": "Gspin-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": cfg["name"], "lattice": list(n), "macro": cfg["macro"]},
+            "roofline": {"bound": "hbm", "kernel": "whole Heun step", "achieved":
+                         round(per_spin * spins / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(per_spin * spins / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic": None},
+            "max_norm_error": norm_err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the short serving sample")
+    ap.add_argument("--workload", default="thin_film", choices=("thin_film", "large_film", "atomistic"),
+                    help="thin_film (default): 512x512x16 RK4 LLG; large_film: 1024x1024x32 "
+                         "demag_field; atomistic: 1024x1024x256 spins, Heun, 4^3 macrocells")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="only the full serving workload: 256 requests x 1000 RK4 steps, "
+                         "Poisson loads 0.5/0.8/0.95 of the closed-loop throughput")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -91,7 +272,21 @@ def main():
     import torch
     import paper_2308_08447_amd as pkg
     import workloads as W
-    from oracle import llg as ollg  # noqa: F401  (gamma constant only via W below)
+
+    if args.serve_full:
+        res = serve_bench(pkg, 256, 1000, (0.5, 0.8, 0.95))
+        print(json.dumps({"metric": "serve p50/p99 latency", "data": "synthetic",
+                          "config": {"workload": "serving: 256 LLG relaxations, meshes "
+                                     "{32..512}^2 x {1,2,4,8}, 1000 RK4 steps each"},
+                          "serve": res}), flush=True)
+        return
+
+    if args.workload == "large_film":
+        print(json.dumps(large_film_bench(pkg, args)), flush=True)
+        return
+    if args.workload == "atomistic":
+        print(json.dumps(atomistic_bench(pkg, args)), flush=True)
+        return
 
     cfg = W.THIN_FILM
     n, cell = cfg["n"], cfg["cell"]
@@ -178,6 +373,9 @@ def main():
         "demag_field_effective_frac": round(b5 / t_field / 1e9 / HBM_PEAK_GBS, 4),
         "llg_cell_steps_per_s": round(cells * args.steps / elapsed, 1),
     }
+    if not args.no_serve:
+        # short sample of the serving workload (64 requests x 100 RK4 steps)
+        out["serve"] = serve_bench(pkg, 64, 100, (0.8,))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, cell)
     print(json.dumps(out), flush=True)

@@ -203,6 +203,55 @@ int demag_get_chunks(demag_plan* plan, int32_t* nchunks);
 int demag_set_variant(demag_plan* plan, int32_t stage, int32_t variant);
 int demag_get_variant(demag_plan* plan, int32_t stage, int32_t* variant);
 
+/* ---- serving: continuous batching of independent LLG simulations --------- */
+/*
+ * A server owns a worker thread and a HIP stream.  Requests (a mesh, LLG
+ * parameters, dt, a number of RK4 steps and an initial magnetisation in host
+ * memory) are queued by serve_submit and admitted while the device memory they
+ * need (FFT workspace, RK4 buffers, m, and the transformed tensor of their mesh
+ * unless an active request already holds it) fits the HBM budget and fewer than
+ * max_active requests run.  Every iteration advances all active requests by the
+ * same number of RK4 steps with shared launches (requests of equal transform
+ * lengths share each FFT-stage launch; one launch updates every mesh's LLG
+ * stage); finished requests are copied back to host memory, their memory is
+ * released and queued requests are admitted.  Each result is bit-identical to
+ * running the same request alone with llg_step.
+ */
+typedef struct demag_server demag_server;
+
+enum {
+    SERVE_GRAPHS = 1          /* replay each active set's step from a captured HIP graph */
+};
+
+typedef struct {
+    uint64_t submitted, completed, failed;
+    int32_t active, queued;
+    double cell_steps;        /* sum over completed requests of cells x steps */
+    size_t bytes_in_use, peak_bytes;
+    uint64_t iterations;      /* worker iterations that advanced active requests */
+    uint64_t graph_captures;  /* graphs captured (one per distinct active set) */
+} serve_stats;
+
+/* hbm_budget_bytes: device memory the server may hold for requests (> 0);
+ * max_active: requests advanced together (1 .. 1024); flags: SERVE_GRAPHS or 0. */
+int serve_open(size_t hbm_budget_bytes, int32_t max_active, uint32_t flags, demag_server** out);
+
+/* Queues a request; copies mesh, params and m0 (host, FP32 [3][nz][ny][nx], unit
+ * vectors) and returns immediately with its id.  Errors: EINVAL, EUNSUPPORTED. */
+int serve_submit(demag_server* srv, const demag_mesh* mesh, const llg_params* params, double dt,
+                 int32_t nsteps, const float* m0_host, uint64_t* request_id);
+
+/* Blocks until the request finishes; copies m (host, same layout as m0) and the
+ * latency from submission to completion (seconds, may be NULL), then forgets
+ * the request.  Returns the request's status (ENOMEM if it can never fit the
+ * budget, or the error that stopped it). */
+int serve_wait(demag_server* srv, uint64_t request_id, float* m_out_host, double* latency_s);
+
+int serve_get_stats(demag_server* srv, serve_stats* out);
+
+/* Stops the worker after the current iteration; unfinished requests are dropped. */
+int serve_close(demag_server* srv);
+
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char* demag_last_error(void);
 

@@ -30,8 +30,10 @@ EXPORTS = (
     "demag_setup", "demag_field", "demag_plan_bytes", "demag_get_kernel", "demag_destroy",
     "llg_step", "atom_setup", "atom_step", "atom_destroy", "demag_timing_enable",
     "demag_timing_read", "demag_autotune", "demag_set_variant", "demag_get_variant",
-    "demag_set_chunks", "demag_get_chunks", "demag_last_error",
+    "demag_set_chunks", "demag_get_chunks", "serve_open", "serve_submit", "serve_wait",
+    "serve_get_stats", "serve_close", "demag_last_error",
 )
+SERVE_GRAPHS = 1
 NVARIANTS = 3
 STAGES = ("x_fwd", "y_fwd", "z_conv", "y_inv", "x_inv", "llg")
 
@@ -54,6 +56,14 @@ class atom_mesh(ctypes.Structure):
 class atom_params(ctypes.Structure):
     _fields_ = [("J", ctypes.c_double), ("mu_s", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("Hzee", ctypes.c_double * 3)]
+
+
+class serve_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("active", ctypes.c_int32), ("queued", ctypes.c_int32),
+                ("cell_steps", ctypes.c_double), ("bytes_in_use", ctypes.c_size_t),
+                ("peak_bytes", ctypes.c_size_t), ("iterations", ctypes.c_uint64),
+                ("graph_captures", ctypes.c_uint64)]
 
 
 class DemagError(RuntimeError):
@@ -100,6 +110,12 @@ def load(path=None):
         "demag_get_variant": ([vp, ctypes.c_int32, P(ctypes.c_int32)], ctypes.c_int),
         "demag_set_chunks": ([vp, ctypes.c_int32], ctypes.c_int),
         "demag_get_chunks": ([vp, P(ctypes.c_int32)], ctypes.c_int),
+        "serve_open": ([sz, ctypes.c_int32, ctypes.c_uint32, P(vp)], ctypes.c_int),
+        "serve_submit": ([vp, P(demag_mesh), P(llg_params), ctypes.c_double, ctypes.c_int32, vp,
+                          P(ctypes.c_uint64)], ctypes.c_int),
+        "serve_wait": ([vp, ctypes.c_uint64, vp, P(ctypes.c_double)], ctypes.c_int),
+        "serve_get_stats": ([vp, P(serve_stats)], ctypes.c_int),
+        "serve_close": ([vp], ctypes.c_int),
         "demag_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -230,6 +246,49 @@ def atom_step(plan, S, params, dt, nsteps, stream=None):
 
 def atom_destroy(plan):
     return _check(load().atom_destroy(plan))
+
+
+def _llg(params):
+    if isinstance(params, llg_params):
+        return params
+    Ms, A, alpha, gamma, hz = params
+    return llg_params(Ms, A, alpha, gamma, (ctypes.c_double * 3)(*hz))
+
+
+def serve_open(hbm_budget_bytes, max_active=64, flags=0):
+    out = ctypes.c_void_p()
+    _check(load().serve_open(int(hbm_budget_bytes), max_active, flags, ctypes.byref(out)))
+    return out.value
+
+
+def serve_submit(server, mesh, params, dt, nsteps, m0_host):
+    """m0_host: C-contiguous float32 numpy array [3][nz][ny][nx] (copied)."""
+    import numpy as np
+    if not isinstance(mesh, demag_mesh):
+        mesh = demag_mesh(*mesh)
+    m0 = np.ascontiguousarray(m0_host, dtype=np.float32)
+    rid = ctypes.c_uint64()
+    _check(load().serve_submit(server, ctypes.byref(mesh), ctypes.byref(_llg(params)), dt, nsteps,
+                               m0.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rid)))
+    return rid.value
+
+
+def serve_wait(server, request_id, m_out_host):
+    """Blocks until done; fills m_out_host (float32, C-contiguous); returns latency in s."""
+    lat = ctypes.c_double()
+    _check(load().serve_wait(server, request_id, m_out_host.ctypes.data_as(ctypes.c_void_p),
+                             ctypes.byref(lat)))
+    return lat.value
+
+
+def serve_get_stats(server):
+    st = serve_stats()
+    _check(load().serve_get_stats(server, ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in serve_stats._fields_}
+
+
+def serve_close(server):
+    return _check(load().serve_close(server))
 
 
 def kernel_shape(n):

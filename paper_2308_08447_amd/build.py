@@ -13,7 +13,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdemag.so")
-SOURCES = ["capi.hip", "stages.hip", "tensor.hip", "dynamics.hip"]
+SOURCES = ["capi.hip", "stages.hip", "tensor.hip", "dynamics.hip", "serve.hip"]
 ARCH = os.environ.get("DEMAG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

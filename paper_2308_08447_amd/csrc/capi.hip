@@ -1,20 +1,22 @@
-// capi.hip -- the extern "C" entry points declared in include/demag.h.
+// capi.hip -- plans, batched field evaluation, RK4 and Heun drivers, and the
+// extern "C" entry points declared in include/demag.h.
 //
-// A plan owns, per mesh: the packed FP32 kernel K, the twiddle tables, the two
-// spectral workspaces S1 and S2 and (allocated on first use) the RK4 stage
-// buffers.  Every entry point validates its arguments on the host before any
-// device work is enqueued and reports failures through a status code and a
-// thread-local message; nothing throws across the ABI.
+// A plan holds, per mesh: a shared reference to the transformed tensor (one
+// copy per mesh and cell size in the process), the two spectral workspaces S1
+// and S2 and, allocated on first use, the RK4 stage buffers.  Every entry point
+// validates its arguments on the host before any device work is enqueued and
+// reports failures through a status code and a thread-local message; nothing
+// throws across the ABI.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
-#include <array>
-#include <map>
-#include <mutex>
+#include <tuple>
 #include <vector>
 
-#include "engine.h"
+#include "plan.h"
 
 namespace dm {
 
@@ -46,7 +48,7 @@ int make_geometry(int nx, int ny, int nz, Geometry* g) {
     return DEMAG_OK;
 }
 
-static int check_mesh(const demag_mesh* m, Geometry* g) {
+int check_mesh(const demag_mesh* m, Geometry* g) {
     if (!m) return fail(DEMAG_EINVAL, "mesh is NULL");
     int rc = make_geometry(m->nx, m->ny, m->nz, g);
     if (rc) return rc;
@@ -56,37 +58,109 @@ static int check_mesh(const demag_mesh* m, Geometry* g) {
     return DEMAG_OK;
 }
 
-}  // namespace dm
+int dev_alloc(void** p, size_t bytes, const char* what) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? DEMAG_ENOMEM : DEMAG_EHIP,
+                    std::string("hipMalloc(") + what + ", " + std::to_string(bytes) +
+                        " B): " + hipGetErrorString(e));
+    }
+    return DEMAG_OK;
+}
 
-using namespace dm;
+// ---------------------------------------------------------------- shared data
+Spectrum::~Spectrum() {
+    if (K) (void)hipFree(K);
+}
 
-struct demag_plan {
-    Geometry g;
-    double dx, dy, dz;
-    uint32_t flags;
-    float* K = nullptr;
-    float2* tw = nullptr;
-    float2* S1 = nullptr;
-    float2* S2 = nullptr;   // chunk buffer of xc kx planes; == S1 (xc = X1) when ny == 1
-    int xc = 1;             // kx planes S2 holds
-    int nch = 1;            // chunks the y/z stages are split into (>= ceil(X1 / xc))
-    // RK4 stage buffers (lazily allocated): H, A, B, acc, each 3 N floats
-    float* rk = nullptr;
-    int device = 0;
-    // per-stage event timing (demag_timing_enable)
-    int timing_cap = 0;
-    std::vector<hipEvent_t> ev[DEMAG_NSTAGES];   // 2 * timing_cap events per stage
-    int timing_n[DEMAG_NSTAGES] = {};
-    int variant[5] = {1, 1, 1, 1, 1};   // tile-shape variant of each FFT stage
-};
+using SpecKey = std::tuple<int, int, int, int, double, double, double>;
+static std::mutex g_spec_mu;
+static std::map<SpecKey, std::weak_ptr<Spectrum>> g_spec;
 
+int get_spectrum(const Geometry& g, double dx, double dy, double dz, hipStream_t s,
+                 std::shared_ptr<Spectrum>* out) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    SpecKey key{dev, g.nx, g.ny, g.nz, dx, dy, dz};
+    std::lock_guard<std::mutex> lk(g_spec_mu);
+    auto it = g_spec.find(key);
+    if (it != g_spec.end()) {
+        if (auto sp = it->second.lock()) {
+            *out = sp;
+            return DEMAG_OK;
+        }
+    }
+    auto sp = std::make_shared<Spectrum>();
+    sp->g = g;
+    sp->dx = dx;
+    sp->dy = dy;
+    sp->dz = dz;
+    sp->device = dev;
+    int rc = dev_alloc((void**)&sp->K, sp->bytes(), "kernel");
+    if (rc) return rc;
+    rc = compute_kernel(g, dx, dy, dz, sp->K, s);
+    if (rc) return rc;
+    g_spec[key] = sp;
+    *out = sp;
+    return DEMAG_OK;
+}
+
+static constexpr int TW_LMAX = 4096;   // longest padded transform (n_d <= 2048)
+static std::mutex g_tw_mu;
+static std::map<int, float2*> g_tw;    // per device; lives until the process ends
+
+int device_twiddles(const float2** out) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_tw_mu);
+    auto it = g_tw.find(dev);
+    if (it != g_tw.end()) {
+        *out = it->second;
+        return DEMAG_OK;
+    }
+    std::vector<float2> host((size_t)2 * TW_LMAX);
+    fill_twiddles(host.data(), TW_LMAX);
+    float2* d = nullptr;
+    int rc = dev_alloc((void**)&d, host.size() * sizeof(float2), "twiddles");
+    if (rc) return rc;
+    hipError_t e = hipMemcpy(d, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail(DEMAG_EHIP, std::string("twiddle upload: ") + hipGetErrorString(e));
+    }
+    g_tw[dev] = d;
+    *out = d;
+    return DEMAG_OK;
+}
+
+// S2 holds the y/z spectra of a chunk of kx planes, capped at 128 MB so that a
+// chunk's spectra can stay in the 256 MB Infinity Cache.
+static constexpr size_t S2_CHUNK_BYTES = (size_t)128 << 20;
+
+int s2_planes(const Geometry& g) {
+    if (g.ny == 1) return g.X1;
+    size_t plane = (size_t)3 * g.nz * g.Ny * sizeof(float2);
+    size_t planes = S2_CHUNK_BYTES / plane;
+    if (planes < 1) planes = 1;
+    return planes >= (size_t)g.X1 ? g.X1 : (int)planes;
+}
+
+size_t workspace_bytes(const Geometry& g) {
+    size_t b = g.s1_elems() * sizeof(float2);
+    if (g.ny > 1) b += (size_t)3 * g.nz * s2_planes(g) * g.Ny * sizeof(float2);
+    return b;
+}
+
+size_t rk_bytes(const Geometry& g) { return 4 * 3 * g.cells() * sizeof(float); }
+
+// ---------------------------------------------------------------- plans
 struct Tuned {
     std::array<int, 5> variant;
     int nch;
 };
-
-// Variants picked by demag_autotune, shared by every plan of the same mesh size in
-// this process.
+// Variants picked by demag_autotune, shared by later plans of the same mesh size.
 static std::mutex g_tune_mu;
 static std::map<std::array<int, 3>, Tuned> g_tuned;
 
@@ -99,97 +173,20 @@ static void free_timing(demag_plan* p) {
     p->timing_cap = 0;
 }
 
-// Brackets one stage launch with events when timing is enabled.
-struct StageTimer {
-    demag_plan* p;
-    int stage;
-    hipStream_t s;
-    int slot = -1;
-    StageTimer(demag_plan* p_, int stage_, hipStream_t s_) : p(p_), stage(stage_), s(s_) {
-        if (p->timing_cap > 0 && p->timing_n[stage] < p->timing_cap) {
-            slot = p->timing_n[stage]++;
-            (void)hipEventRecord(p->ev[stage][2 * slot], s);
-        }
-    }
-    ~StageTimer() {
-        if (slot >= 0) (void)hipEventRecord(p->ev[stage][2 * slot + 1], s);
-    }
-};
-
-struct atom_plan {
-    atom_mesh mesh;
-    demag_plan* dp = nullptr;
-    float* Mm = nullptr;    // macrocell magnetisation (3 Nm)
-    float* Hd0 = nullptr;   // macrocell H_d for S (3 Nm)
-    float* Hd1 = nullptr;   // macrocell H_d for S_p (3 Nm)
-    float* Sp = nullptr;    // predictor spins (3 N)
-    float* f0 = nullptr;    // predictor slope (3 N)
-};
-
-// hipMalloc with the HIP error text in the failure message
-static int dev_alloc(void** p, size_t bytes, const char* what) {
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return fail(e == hipErrorOutOfMemory ? DEMAG_ENOMEM : DEMAG_EHIP,
-                    std::string("hipMalloc(") + what + ", " + std::to_string(bytes) +
-                        " B): " + hipGetErrorString(e));
-    }
-    return DEMAG_OK;
-}
-
-static void free_plan(demag_plan* p) {
+void free_plan(demag_plan* p) {
     if (!p) return;
     free_timing(p);
-    (void)hipFree(p->K);
-    (void)hipFree(p->tw);
     (void)hipFree(p->S1);
     if (p->S2 != p->S1) (void)hipFree(p->S2);
     (void)hipFree(p->rk);
     delete p;
 }
 
-// S2 holds the y/z spectra of a chunk of kx planes.  Its size is capped so a
-// chunk's spectra stay resident in the 256 MB Infinity Cache while the chunk's
-// y FFT, z convolution and y IFFT run back to back.
-static constexpr size_t S2_CHUNK_BYTES = (size_t)128 << 20;
-
-static int s2_planes(const Geometry& g) {
-    if (g.ny == 1) return g.X1;
-    size_t plane = (size_t)3 * g.nz * g.Ny * sizeof(float2);
-    size_t planes = S2_CHUNK_BYTES / plane;
-    if (planes < 1) planes = 1;
-    return planes >= (size_t)g.X1 ? g.X1 : (int)planes;
-}
-
-static size_t plan_bytes(const Geometry& g) {
-    size_t b = g.k_elems() * sizeof(float);
-    b += (size_t)2 * twiddle_table_length(g) * sizeof(float2);
-    b += g.s1_elems() * sizeof(float2);
-    if (g.ny > 1) b += (size_t)3 * g.nz * s2_planes(g) * g.Ny * sizeof(float2);
-    return b;
-}
-
-extern "C" {
-
-const char* demag_last_error(void) { return g_last_error.c_str(); }
-
-size_t demag_plan_bytes(const demag_mesh* mesh, uint32_t flags) {
-    Geometry g;
-    if (flags != DEMAG_FP32) return 0;
-    if (check_mesh(mesh, &g) != DEMAG_OK) return 0;
-    return plan_bytes(g);
-}
-
-int demag_setup(const demag_mesh* mesh, uint32_t flags, void* stream, demag_plan** out) {
-    if (!out) return fail(DEMAG_EINVAL, "out is NULL");
+int create_plan(const demag_mesh* mesh, uint32_t flags, hipStream_t s, demag_plan** out) {
     *out = nullptr;
     Geometry g;
     int rc = check_mesh(mesh, &g);
     if (rc) return rc;
-    if (flags != DEMAG_FP32) return fail(DEMAG_EUNSUPPORTED, "unknown flags");
-    hipStream_t s = (hipStream_t)stream;
     demag_plan* p = new (std::nothrow) demag_plan();
     if (!p) return fail(DEMAG_ENOMEM, "host allocation failed");
     p->g = g;
@@ -202,9 +199,8 @@ int demag_setup(const demag_mesh* mesh, uint32_t flags, void* stream, demag_plan
         free_plan(p);
         return code;
     };
-    if ((rc = dev_alloc((void**)&p->K, g.k_elems() * sizeof(float), "kernel")) ||
-        (rc = dev_alloc((void**)&p->S1, g.s1_elems() * sizeof(float2), "S1")))
-        return bail(rc);
+    if ((rc = device_twiddles(&p->tw))) return bail(rc);
+    if ((rc = dev_alloc((void**)&p->S1, g.s1_elems() * sizeof(float2), "S1"))) return bail(rc);
     p->xc = s2_planes(g);
     p->nch = (g.X1 + p->xc - 1) / p->xc;
     if (g.ny > 1) {
@@ -213,15 +209,7 @@ int demag_setup(const demag_mesh* mesh, uint32_t flags, void* stream, demag_plan
     } else {
         p->S2 = p->S1;
     }
-    int Lmax = twiddle_table_length(g);
-    std::vector<float2> tw((size_t)2 * Lmax);
-    fill_twiddles(tw.data(), Lmax);
-    if ((rc = dev_alloc((void**)&p->tw, tw.size() * sizeof(float2), "twiddles"))) return bail(rc);
-    if (hipMemcpyAsync(p->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice, s) !=
-        hipSuccess)
-        return bail(fail(DEMAG_EHIP, "twiddle upload failed"));
-    rc = compute_kernel(g, mesh->dx, mesh->dy, mesh->dz, p->K, s);
-    if (rc) return bail(rc);
+    if ((rc = get_spectrum(g, mesh->dx, mesh->dy, mesh->dz, s, &p->spec))) return bail(rc);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find({g.nx, g.ny, g.nz});
@@ -234,62 +222,296 @@ int demag_setup(const demag_mesh* mesh, uint32_t flags, void* stream, demag_plan
     return DEMAG_OK;
 }
 
-int demag_destroy(demag_plan* plan) {
-    if (!plan) return fail(DEMAG_EINVAL, "plan is NULL");
-    free_plan(plan);
-    return DEMAG_OK;
+int ensure_rk(demag_plan* p) {
+    if (p->rk) return DEMAG_OK;
+    return dev_alloc((void**)&p->rk, rk_bytes(p->g), "RK4 buffers");
 }
 
-}  // extern "C"
+// Brackets one stage launch with events when timing is enabled on the plan.
+struct StageTimer {
+    demag_plan* p;
+    int stage;
+    hipStream_t s;
+    int slot = -1;
+    StageTimer(demag_plan* p_, int stage_, hipStream_t s_) : p(p_), stage(stage_), s(s_) {
+        if (p && p->timing_cap > 0 && p->timing_n[stage] < p->timing_cap) {
+            slot = p->timing_n[stage]++;
+            (void)hipEventRecord(p->ev[stage][2 * slot], s);
+        }
+    }
+    ~StageTimer() {
+        if (slot >= 0) (void)hipEventRecord(p->ev[stage][2 * slot + 1], s);
+    }
+};
 
-static StageArgs stage_args(demag_plan* p, hipStream_t s) {
-    StageArgs a{&p->g, p->tw, p->S1, p->S2, p->K, s, {}, p->xc};
-    for (int i = 0; i < 5; ++i) a.variant[i] = p->variant[i];
-    return a;
+static XDesc xdesc(demag_plan* p, const float* M, float* H, float scale) {
+    return XDesc{M, H, p->S1, p->g.ny, p->g.nz, scale};
+}
+static YDesc ydesc(demag_plan* p, int k0, int nk) {
+    return YDesc{p->S1, p->S2, p->g.X1, p->g.nz, k0, nk, p->xc};
+}
+static ZDesc zdesc(demag_plan* p, int k0, int nk) {
+    return ZDesc{p->S2, p->spec->K, p->g.X1, p->g.Ny, p->g.Y1, p->g.Z1, k0, nk, p->xc};
+}
+template <class D>
+static StageBatch<D> one(const D& d) {
+    StageBatch<D> b;
+    b.d[0] = d;
+    b.count = 1;
+    return b;
 }
 
-// x R2C over the whole mesh; then, chunk by chunk of kx planes, y FFT -> z
-// convolution -> y IFFT through the chunk buffer; then x C2R.
-static int run_field(demag_plan* p, const float* M, float* H, float scale, hipStream_t s) {
+// One plan: x R2C over the whole mesh; then, chunk by chunk of kx planes, y FFT
+// -> z convolution -> y IFFT through the chunk buffer; then x C2R.
+static int run_field_single(demag_plan* p, const float* M, float* H, float scale, hipStream_t s) {
     const Geometry& g = p->g;
-    StageArgs a = stage_args(p, s);
     int rc;
     {
         StageTimer t(p, DEMAG_STAGE_X_FWD, s);
-        if ((rc = launch_x_forward(a, M, scale))) return rc;
+        if ((rc = launch_x_forward(one(xdesc(p, M, H, scale)), g.nx, p->variant[0], p->tw, s))) return rc;
     }
     if (g.ny == 1) {
         StageTimer t(p, DEMAG_STAGE_Z_CONV, s);
-        if ((rc = launch_z_convolve(a, 0, g.X1))) return rc;
+        if ((rc = launch_z_convolve(one(zdesc(p, 0, g.X1)), g.Nz, p->variant[2], p->tw, s))) return rc;
     } else {
         const int per = (g.X1 + p->nch - 1) / p->nch;
         for (int k0 = 0; k0 < g.X1; k0 += per) {
             const int nk = per < g.X1 - k0 ? per : g.X1 - k0;
             {
                 StageTimer t(p, DEMAG_STAGE_Y_FWD, s);
-                if ((rc = launch_y_forward(a, k0, nk))) return rc;
+                if ((rc = launch_y_forward(one(ydesc(p, k0, nk)), g.ny, p->variant[1], p->tw, s))) return rc;
             }
             {
                 StageTimer t(p, DEMAG_STAGE_Z_CONV, s);
-                if ((rc = launch_z_convolve(a, k0, nk))) return rc;
+                if ((rc = launch_z_convolve(one(zdesc(p, k0, nk)), g.Nz, p->variant[2], p->tw, s))) return rc;
             }
             {
                 StageTimer t(p, DEMAG_STAGE_Y_INV, s);
-                if ((rc = launch_y_inverse(a, k0, nk))) return rc;
+                if ((rc = launch_y_inverse(one(ydesc(p, k0, nk)), g.ny, p->variant[3], p->tw, s))) return rc;
             }
         }
     }
     StageTimer t(p, DEMAG_STAGE_X_INV, s);
-    return launch_x_inverse(a, H);
+    return launch_x_inverse(one(xdesc(p, M, H, scale)), g.nx, p->variant[4], p->tw, s);
 }
 
+// Groups item indices by a key, keeping first-appearance order, in runs of at most MAXB.
+template <class KeyFn>
+static std::vector<std::vector<int>> groups(const std::vector<int>& items, KeyFn key) {
+    std::vector<std::vector<int>> out;
+    std::map<long long, size_t> open;
+    for (int i : items) {
+        long long k = key(i);
+        auto it = open.find(k);
+        if (it == open.end() || out[it->second].size() == (size_t)MAXB) {
+            open[k] = out.size();
+            out.push_back({i});
+        } else {
+            out[it->second].push_back(i);
+        }
+    }
+    return out;
+}
+
+int run_fields(demag_plan* const* plans, const float* const* M, float* const* H,
+               const float* scale, int n, hipStream_t s) {
+    if (n == 1) return run_field_single(plans[0], M[0], H[0], scale[0], s);
+    int rc;
+    std::vector<int> items;
+    for (int i = 0; i < n; ++i) {
+        const demag_plan* p = plans[i];
+        if (p->g.ny > 1 && p->nch > 1) {  // several chunks: not batched
+            if ((rc = run_field_single(plans[i], M[i], H[i], scale[i], s))) return rc;
+        } else {
+            items.push_back(i);
+        }
+    }
+    if (items.empty()) return DEMAG_OK;
+    const float2* tw = plans[items[0]]->tw;
+    auto by_nx = groups(items, [&](int i) { return plans[i]->g.nx; });
+    std::vector<int> yitems;
+    for (int i : items)
+        if (plans[i]->g.ny > 1) yitems.push_back(i);
+    auto by_ny = groups(yitems, [&](int i) { return plans[i]->g.ny; });
+    auto by_nz = groups(items, [&](int i) { return plans[i]->g.Nz; });
+    for (auto& grp : by_nx) {
+        XBatch b;
+        b.count = (int)grp.size();
+        for (int r = 0; r < b.count; ++r) b.d[r] = xdesc(plans[grp[r]], M[grp[r]], H[grp[r]], scale[grp[r]]);
+        if ((rc = launch_x_forward(b, plans[grp[0]]->g.nx, plans[grp[0]]->variant[0], tw, s))) return rc;
+    }
+    for (auto& grp : by_ny) {
+        YBatch b;
+        b.count = (int)grp.size();
+        for (int r = 0; r < b.count; ++r) b.d[r] = ydesc(plans[grp[r]], 0, plans[grp[r]]->g.X1);
+        if ((rc = launch_y_forward(b, plans[grp[0]]->g.ny, plans[grp[0]]->variant[1], tw, s))) return rc;
+    }
+    for (auto& grp : by_nz) {
+        ZBatch b;
+        b.count = (int)grp.size();
+        for (int r = 0; r < b.count; ++r) b.d[r] = zdesc(plans[grp[r]], 0, plans[grp[r]]->g.X1);
+        if ((rc = launch_z_convolve(b, plans[grp[0]]->g.Nz, plans[grp[0]]->variant[2], tw, s))) return rc;
+    }
+    for (auto& grp : by_ny) {
+        YBatch b;
+        b.count = (int)grp.size();
+        for (int r = 0; r < b.count; ++r) b.d[r] = ydesc(plans[grp[r]], 0, plans[grp[r]]->g.X1);
+        if ((rc = launch_y_inverse(b, plans[grp[0]]->g.ny, plans[grp[0]]->variant[3], tw, s))) return rc;
+    }
+    for (auto& grp : by_nx) {
+        XBatch b;
+        b.count = (int)grp.size();
+        for (int r = 0; r < b.count; ++r) b.d[r] = xdesc(plans[grp[r]], M[grp[r]], H[grp[r]], scale[grp[r]]);
+        if ((rc = launch_x_inverse(b, plans[grp[0]]->g.nx, plans[grp[0]]->variant[4], tw, s))) return rc;
+    }
+    return DEMAG_OK;
+}
+
+static LLGDesc llg_desc(const LLGStep& st, const float* ms, float* out) {
+    const demag_plan* p = st.plan;
+    const Geometry& g = p->g;
+    const size_t n3 = 3 * g.cells();
+    const double mu0 = 4e-7 * 3.141592653589793238462643383279502884;
+    const double cex = 2.0 * st.prm.A / (mu0 * st.prm.Ms);
+    LLGDesc d;
+    d.m = st.m;
+    d.ms = ms;
+    d.Hd = p->rk;
+    d.acc = p->rk + 3 * n3;
+    d.out = out;
+    d.nx = g.nx;
+    d.ny = g.ny;
+    d.nz = g.nz;
+    d.cx = g.nx > 1 ? (float)(cex / (p->dx * p->dx)) : 0.f;
+    d.cy = g.ny > 1 ? (float)(cex / (p->dy * p->dy)) : 0.f;
+    d.cz = g.nz > 1 ? (float)(cex / (p->dz * p->dz)) : 0.f;
+    for (int k = 0; k < 3; ++k) d.hz[k] = (float)st.prm.Hzee[k];
+    d.gam = (float)(st.prm.gamma / (1.0 + st.prm.alpha * st.prm.alpha));
+    d.alpha = (float)st.prm.alpha;
+    d.dt = (float)st.dt;
+    return d;
+}
+
+int rk4_step_batch(const LLGStep* steps, int n, hipStream_t s) {
+    int rc;
+    for (int i = 0; i < n; ++i)
+        if ((rc = ensure_rk(steps[i].plan))) return rc;
+    std::vector<demag_plan*> plans(n);
+    std::vector<const float*> ms(n);
+    std::vector<float*> hd(n), outs(n);
+    std::vector<float> scale(n);
+    for (int i = 0; i < n; ++i) {
+        plans[i] = steps[i].plan;
+        hd[i] = steps[i].plan->rk;
+        scale[i] = (float)steps[i].prm.Ms;
+    }
+    // stage inputs: m, A, B, A; stage outputs: A, B, A, m (the last one in place)
+    for (int st = 0; st < 4; ++st) {
+        for (int i = 0; i < n; ++i) {
+            const size_t n3 = 3 * plans[i]->g.cells();
+            float* A = plans[i]->rk + n3;
+            float* B = plans[i]->rk + 2 * n3;
+            const float* in[4] = {steps[i].m, A, B, A};
+            float* out[4] = {A, B, A, steps[i].m};
+            ms[i] = in[st];
+            outs[i] = out[st];
+        }
+        if ((rc = run_fields(plans.data(), ms.data(), hd.data(), scale.data(), n, s))) return rc;
+        for (int i0 = 0; i0 < n; i0 += MAXB) {
+            LLGBatch b;
+            b.count = std::min(MAXB, n - i0);
+            for (int r = 0; r < b.count; ++r) b.d[r] = llg_desc(steps[i0 + r], ms[i0 + r], outs[i0 + r]);
+            StageTimer t(n == 1 ? plans[0] : nullptr, DEMAG_STAGE_LLG, s);
+            if ((rc = launch_llg_stage(b, st, s))) return rc;
+        }
+    }
+    return DEMAG_OK;
+}
+
+int check_llg_params(const llg_params* prm, double dt, int32_t nsteps) {
+    if (!prm) return fail(DEMAG_EINVAL, "params must be non-NULL");
+    if (nsteps < 0) return fail(DEMAG_EINVAL, "nsteps must be >= 0");
+    if (!std::isfinite(dt)) return fail(DEMAG_EINVAL, "dt must be finite");
+    if (!(prm->Ms > 0.0) || !(prm->gamma > 0.0) || !(prm->alpha >= 0.0) || !std::isfinite(prm->A) ||
+        !std::isfinite(prm->Ms) || !std::isfinite(prm->gamma) || !std::isfinite(prm->alpha))
+        return fail(DEMAG_EINVAL, "invalid LLG parameters (Ms > 0, gamma > 0, alpha >= 0)");
+    for (double h : prm->Hzee)
+        if (!std::isfinite(h)) return fail(DEMAG_EINVAL, "Hzee must be finite");
+    return DEMAG_OK;
+}
+
+}  // namespace dm
+
+using namespace dm;
+
+struct atom_plan {
+    atom_mesh mesh;
+    demag_plan* dp = nullptr;
+    float* Mm = nullptr;    // macrocell magnetisation (3 Nm)
+    float* Hd0 = nullptr;   // macrocell H_d for S (3 Nm)
+    float* Hd1 = nullptr;   // macrocell H_d for S_p (3 Nm)
+    float* Sp = nullptr;    // predictor spins (3 N)
+    float* f0 = nullptr;    // predictor slope (3 N)
+};
+
 extern "C" {
+
+const char* demag_last_error(void) { return g_last_error.c_str(); }
+
+size_t demag_plan_bytes(const demag_mesh* mesh, uint32_t flags) {
+    Geometry g;
+    if (flags != DEMAG_FP32) return 0;
+    if (check_mesh(mesh, &g) != DEMAG_OK) return 0;
+    return g.k_elems() * sizeof(float) + workspace_bytes(g);
+}
+
+int demag_setup(const demag_mesh* mesh, uint32_t flags, void* stream, demag_plan** out) {
+    if (!out) return fail(DEMAG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (flags != DEMAG_FP32) {
+        Geometry g;
+        int rc = check_mesh(mesh, &g);
+        if (rc) return rc;
+        return fail(DEMAG_EUNSUPPORTED, "unknown flags");
+    }
+    int rc = create_plan(mesh, flags, (hipStream_t)stream, out);
+    if (rc) return rc;
+    DM_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return DEMAG_OK;
+}
+
+int demag_destroy(demag_plan* plan) {
+    if (!plan) return fail(DEMAG_EINVAL, "plan is NULL");
+    free_plan(plan);
+    return DEMAG_OK;
+}
 
 int demag_field(demag_plan* plan, const float* M, float* H, void* stream) {
     if (!plan) return fail(DEMAG_EINVAL, "plan is NULL");
     if (!M || !H) return fail(DEMAG_EINVAL, "M and H must be non-NULL device pointers");
     if ((const void*)M == (const void*)H) return fail(DEMAG_EINVAL, "H must not alias M");
-    return run_field(plan, M, H, 1.0f, (hipStream_t)stream);
+    const float one_scale = 1.0f;
+    return run_fields(&plan, &M, &H, &one_scale, 1, (hipStream_t)stream);
+}
+
+int demag_get_kernel(demag_plan* plan, float* dst, size_t count, void* stream) {
+    if (!plan || !dst) return fail(DEMAG_EINVAL, "plan and dst must be non-NULL");
+    size_t n = plan->g.k_elems();
+    if (count < n) return fail(DEMAG_EINVAL, "dst too small for the packed kernel");
+    DM_HIP(hipMemcpyAsync(dst, plan->spec->K, n * sizeof(float), hipMemcpyDeviceToDevice,
+                          (hipStream_t)stream));
+    return DEMAG_OK;
+}
+
+int llg_step(demag_plan* plan, float* m, const llg_params* prm, double dt, int32_t nsteps,
+             void* stream) {
+    if (!plan || !m) return fail(DEMAG_EINVAL, "plan and m must be non-NULL");
+    int rc = check_llg_params(prm, dt, nsteps);
+    if (rc) return rc;
+    LLGStep st{plan, m, *prm, dt};
+    for (int step = 0; step < nsteps; ++step)
+        if ((rc = rk4_step_batch(&st, 1, (hipStream_t)stream))) return rc;
+    return DEMAG_OK;
 }
 
 int demag_set_variant(demag_plan* plan, int32_t stage, int32_t variant) {
@@ -345,7 +567,6 @@ int demag_autotune(demag_plan* plan, void* stream) {
     }
     const int saved_cap = plan->timing_cap;
     plan->timing_cap = 0;  // no per-stage events while tuning
-    // times `reps` runs of fn on the stream
     auto time_it = [&](auto&& fn, int reps, double* ms_out) -> int {
         int r;
         if ((r = fn())) return r;  // warm-up
@@ -360,23 +581,21 @@ int demag_autotune(demag_plan* plan, void* stream) {
         return DEMAG_OK;
     };
     // 1. tile variants, stage by stage, on the first chunk
-    if ((rc = run_field(plan, M, H, 1.0f, s))) { cleanup(); plan->timing_cap = saved_cap; return rc; }
+    rc = run_field_single(plan, M, H, 1.0f, s);
     const int per = (g.X1 + plan->nch - 1) / plan->nch;
     for (int st = 0; st < 5 && !rc; ++st) {
         if ((st == 1 || st == 3) && g.ny == 1) continue;
         double best = 1e30;
         int best_v = plan->variant[st];
         for (int v = 0; v < NVARIANTS && !rc; ++v) {
-            plan->variant[st] = v;
-            StageArgs a = stage_args(plan, s);
             const int nk = g.ny == 1 ? g.X1 : per;
             auto fn = [&]() -> int {
                 switch (st) {
-                    case 0: return launch_x_forward(a, M, 1.0f);
-                    case 1: return launch_y_forward(a, 0, nk);
-                    case 2: return launch_z_convolve(a, 0, nk);
-                    case 3: return launch_y_inverse(a, 0, nk);
-                    default: return launch_x_inverse(a, H);
+                    case 0: return launch_x_forward(one(xdesc(plan, M, H, 1.0f)), g.nx, v, plan->tw, s);
+                    case 1: return launch_y_forward(one(ydesc(plan, 0, nk)), g.ny, v, plan->tw, s);
+                    case 2: return launch_z_convolve(one(zdesc(plan, 0, nk)), g.Nz, v, plan->tw, s);
+                    case 3: return launch_y_inverse(one(ydesc(plan, 0, nk)), g.ny, v, plan->tw, s);
+                    default: return launch_x_inverse(one(xdesc(plan, M, H, 1.0f)), g.nx, v, plan->tw, s);
                 }
             };
             double ms = 0.0;
@@ -396,7 +615,7 @@ int demag_autotune(demag_plan* plan, void* stream) {
         for (int n = nmin; n <= 8 * nmin && n <= g.X1 && !rc; n *= 2) {
             plan->nch = n;
             double ms = 0.0;
-            rc = time_it([&]() { return run_field(plan, M, H, 1.0f, s); }, 3, &ms);
+            rc = time_it([&]() { return run_field_single(plan, M, H, 1.0f, s); }, 3, &ms);
             if (!rc && ms < best) {
                 best = ms;
                 best_n = n;
@@ -447,65 +666,6 @@ int demag_timing_read(demag_plan* plan, double* total_ms, int32_t* launches) {
         total_ms[s] = acc;
         launches[s] = plan->timing_n[s];
         plan->timing_n[s] = 0;
-    }
-    return DEMAG_OK;
-}
-
-int demag_get_kernel(demag_plan* plan, float* dst, size_t count, void* stream) {
-    if (!plan || !dst) return fail(DEMAG_EINVAL, "plan and dst must be non-NULL");
-    size_t n = plan->g.k_elems();
-    if (count < n) return fail(DEMAG_EINVAL, "dst too small for the packed kernel");
-    DM_HIP(hipMemcpyAsync(dst, plan->K, n * sizeof(float), hipMemcpyDeviceToDevice,
-                          (hipStream_t)stream));
-    return DEMAG_OK;
-}
-
-int llg_step(demag_plan* plan, float* m, const llg_params* prm, double dt, int32_t nsteps,
-             void* stream) {
-    if (!plan || !m || !prm) return fail(DEMAG_EINVAL, "plan, m and params must be non-NULL");
-    if (nsteps < 0) return fail(DEMAG_EINVAL, "nsteps must be >= 0");
-    if (!std::isfinite(dt)) return fail(DEMAG_EINVAL, "dt must be finite");
-    if (!(prm->Ms > 0.0) || !(prm->gamma > 0.0) || !(prm->alpha >= 0.0) || !std::isfinite(prm->A))
-        return fail(DEMAG_EINVAL, "invalid LLG parameters (Ms > 0, gamma > 0, alpha >= 0)");
-    if (nsteps == 0) return DEMAG_OK;
-    hipStream_t s = (hipStream_t)stream;
-    const Geometry& g = plan->g;
-    const size_t N3 = 3 * g.cells();
-    if (!plan->rk) {
-        int rc = dev_alloc((void**)&plan->rk, 4 * N3 * sizeof(float), "RK4 buffers");
-        if (rc) return rc;
-    }
-    float* Hd = plan->rk;
-    float* bufA = plan->rk + N3;
-    float* bufB = plan->rk + 2 * N3;
-    float* acc = plan->rk + 3 * N3;
-    const double mu0 = 4e-7 * 3.141592653589793238462643383279502884;
-    const double cex = 2.0 * prm->A / (mu0 * prm->Ms);
-    LLGStageArgs a;
-    a.nx = g.nx;
-    a.ny = g.ny;
-    a.nz = g.nz;
-    a.cx = g.nx > 1 ? (float)(cex / (plan->dx * plan->dx)) : 0.f;
-    a.cy = g.ny > 1 ? (float)(cex / (plan->dy * plan->dy)) : 0.f;
-    a.cz = g.nz > 1 ? (float)(cex / (plan->dz * plan->dz)) : 0.f;
-    for (int d = 0; d < 3; ++d) a.hz[d] = (float)prm->Hzee[d];
-    a.gam = (float)(prm->gamma / (1.0 + prm->alpha * prm->alpha));
-    a.alpha = (float)prm->alpha;
-    a.dt = (float)dt;
-    const float Ms = (float)prm->Ms;
-    for (int step = 0; step < nsteps; ++step) {
-        const float* ms = m;
-        float* outs[4] = {bufA, bufB, bufA, m};
-        for (int st = 0; st < 4; ++st) {
-            int rc = run_field(plan, ms, Hd, Ms, s);
-            if (rc) return rc;
-            {
-                StageTimer t(plan, DEMAG_STAGE_LLG, s);
-                rc = launch_llg_stage(a, st, m, ms, Hd, acc, outs[st], s);
-            }
-            if (rc) return rc;
-            ms = outs[st];
-        }
     }
     return DEMAG_OK;
 }
@@ -581,13 +741,15 @@ int atom_step(atom_plan* p, float* S, const atom_params* prm, double dt, int32_t
     a.dt = (float)dt;
     double ns = (double)p->mesh.macro * p->mesh.macro * p->mesh.macro;
     a.mscale = (float)(prm->mu_s * muB / (p->mesh.a * p->mesh.a * p->mesh.a * ns));
+    const float unit = 1.0f;
     for (int step = 0; step < nsteps; ++step) {
         int rc;
+        const float* Mm = p->Mm;
         if ((rc = launch_macro_average(a, S, p->Mm, s))) return rc;
-        if ((rc = run_field(p->dp, p->Mm, p->Hd0, 1.0f, s))) return rc;
+        if ((rc = run_fields(&p->dp, &Mm, &p->Hd0, &unit, 1, s))) return rc;
         if ((rc = launch_heun_predict(a, S, p->Hd0, p->f0, p->Sp, s))) return rc;
         if ((rc = launch_macro_average(a, p->Sp, p->Mm, s))) return rc;
-        if ((rc = run_field(p->dp, p->Mm, p->Hd1, 1.0f, s))) return rc;
+        if ((rc = run_fields(&p->dp, &Mm, &p->Hd1, &unit, 1, s))) return rc;
         if ((rc = launch_heun_correct(a, S, p->Sp, p->f0, p->Hd1, s))) return rc;
     }
     return DEMAG_OK;

@@ -12,15 +12,16 @@ namespace dm {
 namespace {
 
 __device__ __forceinline__ float3 cross3(float3 a, float3 b) {
-    return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+    return make_float3(fmaf(a.y, b.z, -(a.z * b.y)), fmaf(a.z, b.x, -(a.x * b.z)),
+                       fmaf(a.x, b.y, -(a.y * b.x)));
 }
 
 // Landau-Lifshitz right-hand side: -gam [m x H + alpha m x (m x H)]
 __device__ __forceinline__ float3 ll_rhs(float3 m, float3 H, float gam, float alpha) {
     float3 mxH = cross3(m, H);
     float3 mmH = cross3(m, mxH);
-    return make_float3(-gam * (mxH.x + alpha * mmH.x), -gam * (mxH.y + alpha * mmH.y),
-                       -gam * (mxH.z + alpha * mmH.z));
+    return make_float3(-gam * fmaf(alpha, mmH.x, mxH.x), -gam * fmaf(alpha, mmH.y, mxH.y),
+                       -gam * fmaf(alpha, mmH.z, mxH.z));
 }
 
 __device__ __forceinline__ float3 load3(const float* __restrict__ f, size_t i, size_t N) {
@@ -39,60 +40,50 @@ __device__ __forceinline__ void store3(float* __restrict__ f, size_t i, size_t N
 //   s=1: acc += 2 k2,   out = m + dt/2 k2
 //   s=2: acc += 2 k3,   out = m + dt k3
 //   s=3: out = normalise(m + dt/6 (acc + k4))   (out may alias m)
-__global__ __launch_bounds__(256) void llg_stage_kernel(LLGStageArgs a, int stage,
-                                                        const float* m, const float* __restrict__ ms,
-                                                        const float* __restrict__ Hd, float* acc,
-                                                        float* out) {
+// One launch updates a batch of independent meshes (one descriptor each).
+__global__ __launch_bounds__(256) void llg_stage_kernel(const LLGBatch b, int stage) {
+    int item = 0;
+    while (item + 1 < b.count && (int)blockIdx.x >= b.start[item + 1]) ++item;
+    const LLGDesc& a = b.d[item];
     const size_t N = (size_t)a.nx * a.ny * a.nz;
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t i = (size_t)(blockIdx.x - b.start[item]) * blockDim.x + threadIdx.x;
     if (i >= N) return;
+    const float* __restrict__ ms = a.ms;
     int x = (int)(i % a.nx);
     int y = (int)((i / a.nx) % a.ny);
     int z = (int)(i / ((size_t)a.nx * a.ny));
     float3 c = load3(ms, i, N);
     // free boundaries: a missing neighbour is replaced by the cell itself
     float3 lap = make_float3(0.f, 0.f, 0.f);
-    if (a.nx > 1) {
-        float3 l = x > 0 ? load3(ms, i - 1, N) : c;
-        float3 r = x < a.nx - 1 ? load3(ms, i + 1, N) : c;
-        lap.x += a.cx * (l.x + r.x - 2.f * c.x);
-        lap.y += a.cx * (l.y + r.y - 2.f * c.y);
-        lap.z += a.cx * (l.z + r.z - 2.f * c.z);
-    }
-    if (a.ny > 1) {
-        float3 l = y > 0 ? load3(ms, i - a.nx, N) : c;
-        float3 r = y < a.ny - 1 ? load3(ms, i + a.nx, N) : c;
-        lap.x += a.cy * (l.x + r.x - 2.f * c.x);
-        lap.y += a.cy * (l.y + r.y - 2.f * c.y);
-        lap.z += a.cy * (l.z + r.z - 2.f * c.z);
-    }
-    if (a.nz > 1) {
-        size_t pl = (size_t)a.nx * a.ny;
-        float3 l = z > 0 ? load3(ms, i - pl, N) : c;
-        float3 r = z < a.nz - 1 ? load3(ms, i + pl, N) : c;
-        lap.x += a.cz * (l.x + r.x - 2.f * c.x);
-        lap.y += a.cz * (l.y + r.y - 2.f * c.y);
-        lap.z += a.cz * (l.z + r.z - 2.f * c.z);
-    }
-    float3 hd = load3(Hd, i, N);
+    auto add_axis = [&](float coef, bool has_lo, bool has_hi, size_t stride) {
+        float3 l = has_lo ? load3(ms, i - stride, N) : c;
+        float3 r = has_hi ? load3(ms, i + stride, N) : c;
+        lap.x = fmaf(coef, (l.x + r.x) - 2.f * c.x, lap.x);
+        lap.y = fmaf(coef, (l.y + r.y) - 2.f * c.y, lap.y);
+        lap.z = fmaf(coef, (l.z + r.z) - 2.f * c.z, lap.z);
+    };
+    if (a.nx > 1) add_axis(a.cx, x > 0, x < a.nx - 1, 1);
+    if (a.ny > 1) add_axis(a.cy, y > 0, y < a.ny - 1, (size_t)a.nx);
+    if (a.nz > 1) add_axis(a.cz, z > 0, z < a.nz - 1, (size_t)a.nx * a.ny);
+    float3 hd = load3(a.Hd, i, N);
     float3 H = make_float3(hd.x + lap.x + a.hz[0], hd.y + lap.y + a.hz[1], hd.z + lap.z + a.hz[2]);
     float3 k = ll_rhs(c, H, a.gam, a.alpha);
-    float3 m0 = load3(m, i, N);
+    float3 m0 = load3(a.m, i, N);
     if (stage == 0) {
-        store3(acc, i, N, k);
+        store3(a.acc, i, N, k);
         float h = 0.5f * a.dt;
-        store3(out, i, N, make_float3(m0.x + h * k.x, m0.y + h * k.y, m0.z + h * k.z));
+        store3(a.out, i, N, make_float3(fmaf(h, k.x, m0.x), fmaf(h, k.y, m0.y), fmaf(h, k.z, m0.z)));
     } else if (stage < 3) {
-        float3 s = load3(acc, i, N);
-        store3(acc, i, N, make_float3(s.x + 2.f * k.x, s.y + 2.f * k.y, s.z + 2.f * k.z));
+        float3 s = load3(a.acc, i, N);
+        store3(a.acc, i, N, make_float3(fmaf(2.f, k.x, s.x), fmaf(2.f, k.y, s.y), fmaf(2.f, k.z, s.z)));
         float h = stage == 1 ? 0.5f * a.dt : a.dt;
-        store3(out, i, N, make_float3(m0.x + h * k.x, m0.y + h * k.y, m0.z + h * k.z));
+        store3(a.out, i, N, make_float3(fmaf(h, k.x, m0.x), fmaf(h, k.y, m0.y), fmaf(h, k.z, m0.z)));
     } else {
-        float3 s = load3(acc, i, N);
+        float3 s = load3(a.acc, i, N);
         float h = a.dt / 6.f;
-        float3 v = make_float3(m0.x + h * (s.x + k.x), m0.y + h * (s.y + k.y), m0.z + h * (s.z + k.z));
+        float3 v = make_float3(fmaf(h, s.x + k.x, m0.x), fmaf(h, s.y + k.y, m0.y), fmaf(h, s.z + k.z, m0.z));
         float inv = rsqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
-        store3(out, i, N, make_float3(v.x * inv, v.y * inv, v.z * inv));
+        store3(a.out, i, N, make_float3(v.x * inv, v.y * inv, v.z * inv));
     }
 }
 
@@ -186,11 +177,15 @@ unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-int launch_llg_stage(const LLGStageArgs& a, int stage, const float* m, const float* ms,
-                     const float* Hd, float* acc, float* out, hipStream_t stream) {
-    size_t N = (size_t)a.nx * a.ny * a.nz;
-    hipLaunchKernelGGL(llg_stage_kernel, dim3(blocks_for(N)), dim3(256), 0, stream, a, stage, m,
-                       ms, Hd, acc, out);
+int launch_llg_stage(LLGBatch b, int stage, hipStream_t stream) {
+    if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "llg stage: bad batch size");
+    b.start[0] = 0;
+    for (int r = 0; r < b.count; ++r) {
+        size_t N = (size_t)b.d[r].nx * b.d[r].ny * b.d[r].nz;
+        b.start[r + 1] = b.start[r] + (int)blocks_for(N);
+    }
+    hipLaunchKernelGGL(llg_stage_kernel, dim3((unsigned)b.start[b.count]), dim3(256), 0, stream, b,
+                       stage);
     DM_CHECK_LAUNCH();
     return DEMAG_OK;
 }

@@ -38,24 +38,45 @@ struct Geometry {
 int make_geometry(int nx, int ny, int nz, Geometry* g);
 
 // ---- FFT stage launchers (stages.hip) -----------------------------------------
-// tw_all: twiddle tables, length-L table exp(-2 pi i t/L) at tw_all + L.
-struct StageArgs {
-    const Geometry* g;
-    const float2* tw_all;
-    float2* S1;            // [3][nz][X1][ny]
-    float2* S2;            // chunk buffer [3][nz][xc][Ny]; == S1 (xc = X1) when ny == 1
-    const float* K;        // [6][Z1][X1][Y1]
-    hipStream_t stream;
-    int variant[5];        // tile-shape variant per stage (0 .. NVARIANTS-1)
-    int xc;                // kx planes the S2 chunk buffer holds
-};
+// A launch processes a batch of up to MAXB independent work items (one mesh
+// each) that share the stage's transform length; the descriptors travel in the
+// kernel arguments, so launches need no device-side tables and can be captured
+// in graphs.  tw_all: twiddle tables, length-L table exp(-2 pi i t/L) at tw_all + L.
+constexpr int MAXB = 16;
 constexpr int NVARIANTS = 3;
-int launch_x_forward(const StageArgs& a, const float* M, float scale);
-// y / z stages over the kx planes [k0, k0 + nk) (nk <= xc)
-int launch_y_forward(const StageArgs& a, int k0, int nk);
-int launch_z_convolve(const StageArgs& a, int k0, int nk);
-int launch_y_inverse(const StageArgs& a, int k0, int nk);
-int launch_x_inverse(const StageArgs& a, float* H);
+
+struct XDesc {            // x stages: M -> S1 (forward), S1 -> H (inverse)
+    const float* M;
+    float* H;
+    float2* S1;           // [3][nz][X1][ny]
+    int ny, nz;
+    float scale;          // forward input scale (Ms for unit-vector input)
+};
+struct YDesc {            // y stages over kx planes [k0, k0 + nk) of one mesh
+    float2* S1;
+    float2* S2;           // chunk buffer [3][nz][xc][Ny]
+    int X1, nz, k0, nk, xc;
+};
+struct ZDesc {            // z convolution over kx planes [k0, k0 + nk)
+    float2* S2;           // chunk buffer (== S1 with xc = X1 when ny == 1)
+    const float* K;       // [6][Z1][X1][Y1]
+    int X1, Ny, Y1, Z1, k0, nk, xc;
+};
+template <class D>
+struct StageBatch {
+    D d[MAXB];
+    int start[MAXB + 1];  // block prefix sums (filled by the launcher)
+    int count;
+};
+using XBatch = StageBatch<XDesc>;
+using YBatch = StageBatch<YDesc>;
+using ZBatch = StageBatch<ZDesc>;
+
+int launch_x_forward(XBatch b, int nx, int variant, const float2* tw, hipStream_t s);
+int launch_x_inverse(XBatch b, int nx, int variant, const float2* tw, hipStream_t s);
+int launch_y_forward(YBatch b, int ny, int variant, const float2* tw, hipStream_t s);
+int launch_y_inverse(YBatch b, int ny, int variant, const float2* tw, hipStream_t s);
+int launch_z_convolve(ZBatch b, int Nz, int variant, const float2* tw, hipStream_t s);
 // Largest transform length the twiddle table must hold for this geometry.
 int twiddle_table_length(const Geometry& g);
 // Fills the host table (2 * Lmax float2) with exp(-2 pi i t/L) at offset L.
@@ -67,7 +88,12 @@ int compute_kernel(const Geometry& g, double dx, double dy, double dz, float* K,
                    hipStream_t stream);
 
 // ---- dynamics (dynamics.hip) ----------------------------------------------------
-struct LLGStageArgs {
+struct LLGDesc {           // one mesh in a batched RK4 stage update
+    const float* m;        // step start
+    const float* ms;       // stage input
+    const float* Hd;       // demagnetizing field of Ms * ms
+    float* acc;
+    float* out;            // next stage input (may alias m in the last stage)
     int nx, ny, nz;
     float cx, cy, cz;      // 2A/(mu0 Ms h_d^2), 0 for an axis with one cell
     float hz[3];
@@ -75,8 +101,8 @@ struct LLGStageArgs {
     float alpha;
     float dt;
 };
-int launch_llg_stage(const LLGStageArgs& a, int stage, const float* m, const float* ms,
-                     const float* Hd, float* acc, float* out, hipStream_t stream);
+using LLGBatch = StageBatch<LLGDesc>;
+int launch_llg_stage(LLGBatch b, int stage, hipStream_t stream);
 
 struct AtomArgs {
     int nx, ny, nz, macro;

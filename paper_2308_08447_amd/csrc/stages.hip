@@ -52,6 +52,15 @@ __device__ __forceinline__ void load_pair(const float2* s, float2& a, float2& b,
     }
 }
 
+// A batched launch covers several independent work items (requests); item r
+// owns blocks [start[r], start[r+1]) of the (XCD-renumbered) grid.
+template <class B>
+__device__ __forceinline__ int batch_item(const B& b, int gid) {
+    int r = 0;
+    while (r + 1 < b.count && gid >= b.start[r + 1]) ++r;
+    return r;
+}
+
 // Copies n table entries into LDS (issued with the block's data loads; the
 // block's first barrier makes them visible).
 __device__ __forceinline__ void stage_table(float2* dst, const float2* __restrict__ src, int n) {
@@ -65,9 +74,7 @@ __device__ __forceinline__ void stage_table(float2* dst, const float2* __restric
 // the last pass leaves the spectrum in LDS in natural order, from where the
 // Hermitian separation writes S1 transposed (consecutive threads, consecutive y).
 template <int L, int TY>
-__global__ __launch_bounds__(NT) void x_forward_kernel(const float* __restrict__ M,
-                                                       float2* __restrict__ S1, int ny, int nz,
-                                                       float scale,
+__global__ __launch_bounds__(NT) void x_forward_kernel(const XBatch b,
                                                        const float2* __restrict__ tw_all) {
     constexpr int NP = TY / 2;
     constexpr int LS = lpad_c(L) + 1;  // odd stride: the pairs of one frequency hit distinct banks
@@ -76,8 +83,14 @@ __global__ __launch_bounds__(NT) void x_forward_kernel(const float* __restrict__
     const float2* tw2L = tw_all + 2 * L;
     stage_table(twL, tw_all + L, L);
     const int tid = threadIdx.x;
+    const int gid = xcd_tile(blockIdx.x, gridDim.x);
+    const int item = batch_item(b, gid);
+    const float* __restrict__ M = b.d[item].M;
+    float2* __restrict__ S1 = b.d[item].S1;
+    const int ny = b.d[item].ny, nz = b.d[item].nz;
+    const float scale = b.d[item].scale;
     const int nyt = (ny + TY - 1) / TY;
-    const int id = xcd_tile(blockIdx.x, gridDim.x);
+    const int id = gid - b.start[item];
     const int y0 = (id % nyt) * TY, z = (id / nyt) % nz, c = id / (nyt * nz);
     const int rows = min(TY, ny - y0);
     const float* src = M + ((size_t)(c * nz + z) * ny + y0) * L;
@@ -124,8 +137,7 @@ __global__ __launch_bounds__(NT) void x_forward_kernel(const float* __restrict__
 // part is parked in a second LDS region, and the last pass of the odd part
 // combines z[t] = IE[t] + W_2L^-t IO[t] and stores both rows of H directly.
 template <int L, int TY>
-__global__ __launch_bounds__(NT) void x_inverse_kernel(const float2* __restrict__ S1,
-                                                       float* __restrict__ H, int ny, int nz,
+__global__ __launch_bounds__(NT) void x_inverse_kernel(const XBatch b,
                                                        const float2* __restrict__ tw_all) {
     constexpr int NP = TY / 2;
     constexpr int LS = lpad_c(L) + 1;  // odd stride: the pairs of one frequency hit distinct banks
@@ -136,8 +148,13 @@ __global__ __launch_bounds__(NT) void x_inverse_kernel(const float2* __restrict_
     stage_table(twL, tw_all + L, L);
     stage_table(tw2L, tw_all + 2 * L, L);
     const int tid = threadIdx.x;
+    const int gid = xcd_tile(blockIdx.x, gridDim.x);
+    const int item = batch_item(b, gid);
+    const float2* __restrict__ S1 = b.d[item].S1;
+    float* __restrict__ H = b.d[item].H;
+    const int ny = b.d[item].ny, nz = b.d[item].nz;
     const int nyt = (ny + TY - 1) / TY;
-    const int id = xcd_tile(blockIdx.x, gridDim.x);
+    const int id = gid - b.start[item];
     const int y0 = (id % nyt) * TY, z = (id / nyt) % nz, c = id / (nyt * nz);
     const int rows = min(TY, ny - y0);
     const float2* src = S1 + (size_t)(c * nz + z) * (L + 1) * ny + y0;
@@ -199,17 +216,21 @@ __global__ void x_copy_inverse_kernel(const float2* __restrict__ S1, float* __re
 // upper L outputs are dropped (inverse); the first pass reads S1/S2 straight
 // into registers and the last pass stores straight from registers.
 template <int L, int LPB>
-__global__ __launch_bounds__(NT) void y_forward_kernel(const float2* __restrict__ S1,
-                                                       float2* __restrict__ S2, int X1, int nz,
-                                                       int k0, int nk, int xc,
+__global__ __launch_bounds__(NT) void y_forward_kernel(const YBatch b,
                                                        const float2* __restrict__ tw_all) {
     constexpr int LN = 2 * L;
     constexpr int LS = lpad_c(LN);
     __shared__ float2 buf[LPB * LS];
     __shared__ float2 tw[LN];
     stage_table(tw, tw_all + LN, LN);
+    const int gid = xcd_tile(blockIdx.x, gridDim.x);
+    const int item = batch_item(b, gid);
+    const float2* __restrict__ S1 = b.d[item].S1;
+    float2* __restrict__ S2 = b.d[item].S2;
+    const int X1 = b.d[item].X1, nz = b.d[item].nz, k0 = b.d[item].k0, nk = b.d[item].nk;
+    const int xc = b.d[item].xc;
     const int nt = (nk + LPB - 1) / LPB;
-    const int id = xcd_tile(blockIdx.x, gridDim.x);
+    const int id = gid - b.start[item];
     const int kl0 = (id % nt) * LPB, z = (id / nt) % nz, c = id / (nt * nz);
     const int nl = nk - kl0 < LPB ? nk - kl0 : LPB;  // valid lines in this block
     const float2* in = S1 + ((size_t)(c * nz + z) * X1 + k0 + kl0) * L;
@@ -222,17 +243,21 @@ __global__ __launch_bounds__(NT) void y_forward_kernel(const float2* __restrict_
 }
 
 template <int L, int LPB>
-__global__ __launch_bounds__(NT) void y_inverse_kernel(const float2* __restrict__ S2,
-                                                       float2* __restrict__ S1, int X1, int nz,
-                                                       int k0, int nk, int xc,
+__global__ __launch_bounds__(NT) void y_inverse_kernel(const YBatch b,
                                                        const float2* __restrict__ tw_all) {
     constexpr int LN = 2 * L;
     constexpr int LS = lpad_c(LN);
     __shared__ float2 buf[LPB * LS];
     __shared__ float2 tw[LN];
     stage_table(tw, tw_all + LN, LN);
+    const int gid = xcd_tile(blockIdx.x, gridDim.x);
+    const int item = batch_item(b, gid);
+    const float2* __restrict__ S2 = b.d[item].S2;
+    float2* __restrict__ S1 = b.d[item].S1;
+    const int X1 = b.d[item].X1, nz = b.d[item].nz, k0 = b.d[item].k0, nk = b.d[item].nk;
+    const int xc = b.d[item].xc;
     const int nt = (nk + LPB - 1) / LPB;
-    const int id = xcd_tile(blockIdx.x, gridDim.x);
+    const int id = gid - b.start[item];
     const int kl0 = (id % nt) * LPB, z = (id / nt) % nz, c = id / (nt * nz);
     const int nl = nk - kl0 < LPB ? nk - kl0 : LPB;
     const float2* in = S2 + ((size_t)(c * nz + z) * xc + kl0) * LN;
@@ -254,9 +279,7 @@ __global__ __launch_bounds__(NT) void y_inverse_kernel(const float2* __restrict_
 // block is in flight at once), then staged in LDS: element (z, c, column) at
 // z * 3NC + c * NC + column, i.e. 3NC interleaved lines of length NZ.
 template <int NZ, int TH>
-__global__ __launch_bounds__(NT) void z_convolve_kernel(float2* __restrict__ S2,
-                                                        const float* __restrict__ K, int X1,
-                                                        int Ny, int Y1, int Z1, int k0, int xc,
+__global__ __launch_bounds__(NT) void z_convolve_kernel(const ZBatch b,
                                                         const float2* __restrict__ tw_all) {
     constexpr int NZH = NZ > 1 ? NZ / 2 : 1;   // stored z planes
     constexpr int KT = NZ > 1 ? NZ / 2 + 1 : 1;  // folded kz values
@@ -267,10 +290,16 @@ __global__ __launch_bounds__(NT) void z_convolve_kernel(float2* __restrict__ S2,
     __shared__ float2 twZ[NZ];
     stage_table(twZ, tw_all + NZ, NZ);
     const int tid = threadIdx.x;
+    const int gid = xcd_tile(blockIdx.x, gridDim.x);
+    const int item = batch_item(b, gid);
+    float2* __restrict__ S2 = b.d[item].S2;
+    const float* __restrict__ K = b.d[item].K;
+    const int X1 = b.d[item].X1, Ny = b.d[item].Ny, Y1 = b.d[item].Y1, Z1 = b.d[item].Z1;
+    const int k0 = b.d[item].k0, xc = b.d[item].xc;
     const int ny = Ny > 1 ? Ny / 2 : 1;
     const int th = TH < ny ? TH : ny;
     const int nft = ny / th;
-    const int id = xcd_tile(blockIdx.x, gridDim.x);
+    const int id = gid - b.start[item];
     const int f0 = (id % nft) * th, kl = id / nft, kx = k0 + kl;
     const size_t P = (size_t)xc * Ny;  // complex elements per z plane of the chunk
     const size_t cstride = (size_t)NZH * P;
@@ -380,6 +409,11 @@ struct YTile { static constexpr int LPB = 2 * L >= (1024 << V) ? 1 : (1024 << V)
 template <int NZ, int V>
 struct ZTile { static constexpr int TH = (256 << V) / NZ < 1 ? 1 : (256 << V) / NZ; };
 
+template <class B>
+int finish_batch(B& b) {  // prefix sums already in start[]; returns the grid size
+    return b.start[b.count];
+}
+
 }  // namespace
 
 #define DM_POW2_CASES(MACRO) \
@@ -393,23 +427,26 @@ struct ZTile { static constexpr int TH = (256 << V) / NZ < 1 ? 1 : (256 << V) / 
         default: BODY(2) break; \
     }
 
-int launch_x_forward(const StageArgs& a, const float* M, float scale) {
-    const Geometry& g = *a.g;
-    const int variant = a.variant[0];
-    if (g.nx == 1) {
-        size_t n = (size_t)3 * g.nz * g.ny;
-        hipLaunchKernelGGL(x_copy_forward_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                           a.stream, M, a.S1, n, scale);
+int launch_x_forward(XBatch b, int nx, int variant, const float2* tw, hipStream_t s) {
+    if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "x stage: bad batch size");
+    if (nx == 1) {
+        for (int r = 0; r < b.count; ++r) {
+            size_t n = (size_t)3 * b.d[r].nz * b.d[r].ny;
+            hipLaunchKernelGGL(x_copy_forward_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                               s, b.d[r].M, b.d[r].S1, n, b.d[r].scale);
+        }
         DM_CHECK_LAUNCH();
         return DEMAG_OK;
     }
-    switch (g.nx) {
+    switch (nx) {
 #define BODY(V)                                                                               \
     {                                                                                         \
         constexpr int TY = XTile<L, V, false>::TY;                                            \
-        dim3 grid((unsigned)(((g.ny + TY - 1) / TY) * g.nz * 3));                            \
-        hipLaunchKernelGGL((x_forward_kernel<L, TY>), grid, dim3(NT), 0, a.stream, M, a.S1,  \
-                           g.ny, g.nz, scale, a.tw_all);                                      \
+        b.start[0] = 0;                                                                       \
+        for (int r = 0; r < b.count; ++r)                                                     \
+            b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;       \
+        hipLaunchKernelGGL((x_forward_kernel<L, TY>), dim3((unsigned)finish_batch(b)), dim3(NT), \
+                           0, s, b, tw);                                                      \
     }
 #define CASE(Lv)                    \
     case Lv: {                      \
@@ -426,23 +463,26 @@ int launch_x_forward(const StageArgs& a, const float* M, float scale) {
     return DEMAG_OK;
 }
 
-int launch_x_inverse(const StageArgs& a, float* H) {
-    const Geometry& g = *a.g;
-    const int variant = a.variant[4];
-    if (g.nx == 1) {
-        size_t n = (size_t)3 * g.nz * g.ny;
-        hipLaunchKernelGGL(x_copy_inverse_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                           a.stream, a.S1, H, n);
+int launch_x_inverse(XBatch b, int nx, int variant, const float2* tw, hipStream_t s) {
+    if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "x stage: bad batch size");
+    if (nx == 1) {
+        for (int r = 0; r < b.count; ++r) {
+            size_t n = (size_t)3 * b.d[r].nz * b.d[r].ny;
+            hipLaunchKernelGGL(x_copy_inverse_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                               s, b.d[r].S1, b.d[r].H, n);
+        }
         DM_CHECK_LAUNCH();
         return DEMAG_OK;
     }
-    switch (g.nx) {
+    switch (nx) {
 #define BODY(V)                                                                               \
     {                                                                                         \
         constexpr int TY = XTile<L, V, true>::TY;                                             \
-        dim3 grid((unsigned)(((g.ny + TY - 1) / TY) * g.nz * 3));                            \
-        hipLaunchKernelGGL((x_inverse_kernel<L, TY>), grid, dim3(NT), 0, a.stream, a.S1, H,  \
-                           g.ny, g.nz, a.tw_all);                                             \
+        b.start[0] = 0;                                                                       \
+        for (int r = 0; r < b.count; ++r)                                                     \
+            b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;       \
+        hipLaunchKernelGGL((x_inverse_kernel<L, TY>), dim3((unsigned)finish_batch(b)), dim3(NT), \
+                           0, s, b, tw);                                                      \
     }
 #define CASE(Lv)                    \
     case Lv: {                      \
@@ -459,17 +499,23 @@ int launch_x_inverse(const StageArgs& a, float* H) {
     return DEMAG_OK;
 }
 
-int launch_y_forward(const StageArgs& a, int k0, int nk) {
-    const Geometry& g = *a.g;
-    const int variant = a.variant[1];
-    if (g.ny == 1) return DEMAG_OK;  // S2 aliases S1
-    switch (g.ny) {
+template <bool INVERSE>
+static int launch_y(YBatch b, int ny, int variant, const float2* tw, hipStream_t s) {
+    if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "y stage: bad batch size");
+    if (ny == 1) return DEMAG_OK;  // no y transform (S2 aliases S1)
+    switch (ny) {
 #define BODY(V)                                                                                 \
     {                                                                                           \
         constexpr int LPB = YTile<L, V>::LPB;                                                   \
-        dim3 grid((unsigned)(((nk + LPB - 1) / LPB) * g.nz * 3));                              \
-        hipLaunchKernelGGL((y_forward_kernel<L, LPB>), grid, dim3(NT), 0, a.stream, a.S1, a.S2, \
-                           g.X1, g.nz, k0, nk, a.xc, a.tw_all);                                 \
+        b.start[0] = 0;                                                                         \
+        for (int r = 0; r < b.count; ++r)                                                       \
+            b.start[r + 1] = b.start[r] + ((b.d[r].nk + LPB - 1) / LPB) * b.d[r].nz * 3;       \
+        if (INVERSE)                                                                            \
+            hipLaunchKernelGGL((y_inverse_kernel<L, LPB>), dim3((unsigned)finish_batch(b)),     \
+                               dim3(NT), 0, s, b, tw);                                          \
+        else                                                                                    \
+            hipLaunchKernelGGL((y_forward_kernel<L, LPB>), dim3((unsigned)finish_batch(b)),     \
+                               dim3(NT), 0, s, b, tw);                                          \
     }
 #define CASE(Lv)                    \
     case Lv: {                      \
@@ -486,44 +532,27 @@ int launch_y_forward(const StageArgs& a, int k0, int nk) {
     return DEMAG_OK;
 }
 
-int launch_y_inverse(const StageArgs& a, int k0, int nk) {
-    const Geometry& g = *a.g;
-    const int variant = a.variant[3];
-    if (g.ny == 1) return DEMAG_OK;
-    switch (g.ny) {
-#define BODY(V)                                                                                 \
-    {                                                                                           \
-        constexpr int LPB = YTile<L, V>::LPB;                                                   \
-        dim3 grid((unsigned)(((nk + LPB - 1) / LPB) * g.nz * 3));                              \
-        hipLaunchKernelGGL((y_inverse_kernel<L, LPB>), grid, dim3(NT), 0, a.stream, a.S2, a.S1, \
-                           g.X1, g.nz, k0, nk, a.xc, a.tw_all);                                 \
-    }
-#define CASE(Lv)                    \
-    case Lv: {                      \
-        constexpr int L = Lv;       \
-        DM_VARIANTS(BODY)           \
-        break;                      \
-    }
-        DM_POW2_CASES(CASE)
-#undef CASE
-#undef BODY
-        default: return fail(DEMAG_EUNSUPPORTED, "y stage: unsupported ny");
-    }
-    DM_CHECK_LAUNCH();
-    return DEMAG_OK;
+int launch_y_forward(YBatch b, int ny, int variant, const float2* tw, hipStream_t s) {
+    return launch_y<false>(b, ny, variant, tw, s);
+}
+int launch_y_inverse(YBatch b, int ny, int variant, const float2* tw, hipStream_t s) {
+    return launch_y<true>(b, ny, variant, tw, s);
 }
 
-int launch_z_convolve(const StageArgs& a, int k0, int nk) {
-    const Geometry& g = *a.g;
-    const int variant = a.variant[2];
-    switch (g.Nz) {
+int launch_z_convolve(ZBatch b, int Nz, int variant, const float2* tw, hipStream_t s) {
+    if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "z stage: bad batch size");
+    switch (Nz) {
 #define BODY(V)                                                                                \
     {                                                                                          \
         constexpr int TH = ZTile<NZ, V>::TH;                                                   \
-        int th = TH < g.ny ? TH : g.ny;                                                        \
-        dim3 grid((unsigned)((g.ny / th) * nk));                                               \
-        hipLaunchKernelGGL((z_convolve_kernel<NZ, TH>), grid, dim3(NT), 0, a.stream, a.S2, a.K, \
-                           g.X1, g.Ny, g.Y1, g.Z1, k0, a.xc, a.tw_all);                        \
+        b.start[0] = 0;                                                                        \
+        for (int r = 0; r < b.count; ++r) {                                                    \
+            int ny = b.d[r].Ny > 1 ? b.d[r].Ny / 2 : 1;                                        \
+            int th = TH < ny ? TH : ny;                                                        \
+            b.start[r + 1] = b.start[r] + (ny / th) * b.d[r].nk;                               \
+        }                                                                                      \
+        hipLaunchKernelGGL((z_convolve_kernel<NZ, TH>), dim3((unsigned)finish_batch(b)),       \
+                           dim3(NT), 0, s, b, tw);                                             \
     }
 #define CASE(NZv)                   \
     case NZv: {                     \

@@ -59,9 +59,9 @@ def test_plan_bytes_formula():
     X1, Y1, Z1 = nx + 1, ny + 1, nz + 1
     plane = 3 * nz * 2 * ny * 8                  # one kx plane of the y/z spectra
     planes = min(X1, (128 << 20) // plane)       # the chunk buffer is capped at 128 MB
-    expect = 6 * Z1 * X1 * Y1 * 4 + 2 * 2 * ny * 8 + 3 * nz * X1 * ny * 8 + planes * plane
+    expect = 6 * Z1 * X1 * Y1 * 4 + 3 * nz * X1 * ny * 8 + planes * plane
     assert pkg.demag_plan_bytes((nx, ny, nz, 4e-9, 4e-9, 4e-9)) == expect
     # small meshes hold every plane
     n = (32, 32, 4)
-    small = 6 * 5 * 33 * 33 * 4 + 2 * 64 * 8 + 3 * 4 * 33 * 32 * 8 + 3 * 4 * 33 * 64 * 8
+    small = 6 * 5 * 33 * 33 * 4 + 3 * 4 * 33 * 32 * 8 + 3 * 4 * 33 * 64 * 8
     assert pkg.demag_plan_bytes(n + (4e-9, 4e-9, 4e-9)) == small

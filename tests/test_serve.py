@@ -1,0 +1,123 @@
+"""Continuous-batching server: each result equals the same request run alone
+(bit for bit), graph replay equals eager launches, admission respects the device
+memory budget, and a request that can never fit fails cleanly."""
+
+import numpy as np
+import pytest
+
+import paper_2308_08447_amd as pkg
+import workloads as W
+from oracle import demag as odemag
+from oracle import llg as ollg
+
+GAMMA = ollg.GAMMA
+CELL = W.CELL_4NM
+
+
+def _mix(count=10, seed=5, max_steps=12):
+    """Seeded request mix: small meshes of uneven size, random alpha and step count."""
+    rng = np.random.default_rng(seed)
+    shapes = [(32, 32, 1), (64, 32, 2), (32, 64, 4), (16, 16, 8), (64, 64, 1), (8, 8, 2), (128, 16, 1)]
+    reqs = []
+    for i in range(count):
+        n = shapes[int(rng.integers(len(shapes)))]
+        alpha = float(rng.uniform(0.01, 0.5))
+        steps = int(rng.integers(3, max_steps))
+        m0 = W.unit_vectors((n[2], n[1], n[0]), seed=100 + i)
+        reqs.append((n, alpha, steps, m0))
+    return reqs
+
+
+def _params(alpha):
+    return (W.MS, W.A_EX, alpha, GAMMA, (0.0, 0.0, 2e4))
+
+
+def _run_server(reqs, flags, budget=8 << 30, max_active=64):
+    srv = pkg.serve_open(budget, max_active, flags)
+    try:
+        ids = [pkg.serve_submit(srv, n + CELL, _params(a), 1e-13, s, m0) for n, a, s, m0 in reqs]
+        outs = []
+        for rid, (n, a, s, m0) in zip(ids, reqs):
+            out = np.empty_like(m0)
+            lat = pkg.serve_wait(srv, rid, out)
+            assert lat > 0
+            outs.append(out)
+        stats = pkg.serve_get_stats(srv)
+    finally:
+        pkg.serve_close(srv)
+    return outs, stats
+
+
+def _alone(n, alpha, steps, m0):
+    import torch
+    plan = pkg.demag_setup(n + CELL)
+    try:
+        m = torch.from_numpy(m0).cuda()
+        pkg.llg_step(plan, m, _params(alpha), 1e-13, steps)
+        torch.cuda.synchronize()
+        return m.cpu().numpy()
+    finally:
+        pkg.demag_destroy(plan)
+
+
+@pytest.mark.gpu
+def test_mixed_results_equal_alone_bitwise(gpu_lib):
+    reqs = _mix()
+    print("serving mix of", len(reqs), "requests (eager launches)", flush=True)
+    outs, stats = _run_server(reqs, flags=0)
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    for (n, a, s, m0), out in zip(reqs, outs):
+        ref = _alone(n, a, s, m0)
+        assert np.array_equal(out, ref), (n, a, s)
+    # one request against the FP64 oracle as well
+    n, a, s, m0 = reqs[0]
+    prob = ollg.LLG(n, CELL, W.MS, W.A_EX, a, Hzee=(0.0, 0.0, 2e4))
+    ref = prob.run(m0.astype(np.float64), 1e-13, s)
+    assert odemag.rel_l2(outs[0].astype(np.float64), ref) <= 2e-5
+
+
+@pytest.mark.gpu
+def test_graph_replay_equals_eager(gpu_lib):
+    reqs = _mix(seed=9)
+    print("serving mix with graph replay", flush=True)
+    eager, _ = _run_server(reqs, flags=0)
+    graphs, stats = _run_server(reqs, flags=pkg.SERVE_GRAPHS)
+    assert stats["graph_captures"] >= 1
+    for a, b in zip(eager, graphs):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.gpu
+def test_budget_admission_and_oversized_request(gpu_lib):
+    reqs = _mix(count=8, seed=3)
+    # a request holds its tensor + FFT workspace (demag_plan_bytes), four RK4
+    # buffers and m (60 bytes per cell); allow about two of the largest at once
+    need = max(pkg.demag_plan_bytes(n + CELL) + 60 * n[0] * n[1] * n[2] for n, _, _, _ in reqs)
+    budget = 2 * need
+    print("serving under a budget of", budget, "bytes", flush=True)
+    outs, stats = _run_server(reqs, flags=0, budget=budget)
+    assert stats["completed"] == len(reqs)
+    assert stats["peak_bytes"] <= budget
+    for (n, a, s, m0), out in zip(reqs, outs):
+        assert np.array_equal(out, _alone(n, a, s, m0))
+    srv = pkg.serve_open(1 << 20, 4, 0)  # 1 MiB: a 256x256x4 mesh can never fit
+    try:
+        m0 = W.unit_vectors((4, 256, 256), seed=1)
+        rid = pkg.serve_submit(srv, (256, 256, 4) + CELL, _params(0.1), 1e-13, 2, m0)
+        with pytest.raises(pkg.DemagError) as e:
+            pkg.serve_wait(srv, rid, np.empty_like(m0))
+        assert e.value.status == pkg.DEMAG_ENOMEM
+    finally:
+        pkg.serve_close(srv)
+
+
+def test_serve_argument_checks_on_host():
+    lib = pkg.load()
+    import ctypes
+    out = ctypes.c_void_p()
+    assert lib.serve_open(0, 4, 0, ctypes.byref(out)) == pkg.DEMAG_EINVAL
+    assert lib.serve_open(1 << 30, 0, 0, ctypes.byref(out)) == pkg.DEMAG_EINVAL
+    assert lib.serve_open(1 << 30, 4, 99, ctypes.byref(out)) == pkg.DEMAG_EINVAL
+    rid = ctypes.c_uint64()
+    assert lib.serve_submit(None, None, None, 1e-13, 1, None, ctypes.byref(rid)) == pkg.DEMAG_EINVAL
+    assert lib.serve_close(None) == pkg.DEMAG_EINVAL
