@@ -62,3 +62,18 @@ def serve_requests(count, seed):
     alphas = rng.uniform(0.01, 0.5, size=count)
     seeds = rng.integers(0, 2**31 - 1, size=count)
     return list(zip(shapes, alphas.tolist(), seeds.tolist()))
+
+
+def sparse_sources(n, nsrc, ntgt, seed):
+    """M = MS x random unit vectors in `nsrc` distinct random cells of the mesh
+    n = (nx, ny, nz), zero elsewhere, as float32 [3][nz][ny][nx]; also the
+    source cells and `ntgt` random target cells, each as rows (x, y, z)."""
+    nx, ny, nz = n
+    rng = np.random.default_rng(seed)
+    flat = rng.choice(nx * ny * nz, size=nsrc, replace=False)
+    src = np.stack([flat % nx, (flat // nx) % ny, flat // (nx * ny)], 1)
+    M = np.zeros((3, nz, ny, nx), dtype=np.float32)
+    M[:, src[:, 2], src[:, 1], src[:, 0]] = unit_vectors((nsrc,), seed) * np.float32(MS)
+    tg = np.stack([rng.integers(0, nx, ntgt), rng.integers(0, ny, ntgt),
+                   rng.integers(0, nz, ntgt)], 1)
+    return M, src, tg
