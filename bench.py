@@ -25,6 +25,41 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+ROOT = os.path.dirname(os.path.abspath(__file__))
+# sources whose change invalidates a stored hardware-counter measurement
+KERNEL_SOURCES = ["paper_2308_08447_amd/csrc/" + f for f in (
+    "stages_x.hip", "stages_y.hip", "stages_z.hip", "stage_common.h", "fft_lds.h", "mfma_dft.h",
+    "engine.h", "dynamics.hip")]
+COUNTERS = "profiles/counters_thin_film_512x512x16.md"
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic(stage):
+    """HBM bytes per launch of `stage` from the stored rocprofv3 counter runs
+    (FETCH_SIZE x its copy-kernel calibration + WRITE_SIZE), or None when no
+    measurement is stored or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, COUNTERS)
+    if not os.path.exists(path):
+        return None
+    vals, sha = {}, None
+    with open(path) as f:
+        for line in f:
+            p = line.split()
+            if len(p) == 3 and p[0] == "traffic_bytes_per_launch":
+                vals[p[1]] = float(p[2])
+            elif len(p) == 2 and p[0] == "kernel_sources_sha256":
+                sha = p[1]
+    if sha != kernel_sources_sha256():
+        return None
+    return vals.get(stage)
 
 
 def geometry(n):
@@ -150,41 +185,219 @@ def _stage_table(nbytes, stages, evals):
     return per_stage
 
 
+def _field_run(pkg, n, cell, flags, M, H, args, stream, label):
+    """Autotuned demag_field on one mesh: per-stage event timing over args.steps
+    evaluations, then the same number untimed.  Returns (seconds per
+    evaluation, per-stage table, chunk count)."""
+    import torch
+    print(f"{label}: set-up", file=sys.stderr, flush=True)
+    plan = pkg.demag_setup(n + cell, flags, stream=stream)
+    try:
+        pkg.demag_autotune(plan, stream)
+        nch = pkg.demag_get_chunks(plan)
+        print(f"{label}: timing", file=sys.stderr, flush=True)
+        for _ in range(args.warmup):
+            pkg.demag_field(plan, M, H, stream)
+        torch.cuda.synchronize()
+        pkg.demag_timing_enable(plan, args.steps * nch)
+        for _ in range(args.steps):
+            pkg.demag_field(plan, M, H, stream)
+        torch.cuda.synchronize()
+        stages = pkg.demag_timing_read(plan)
+        pkg.demag_timing_enable(plan, 0)
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            pkg.demag_field(plan, M, H, stream)
+        torch.cuda.synchronize()
+        t_field = (time.perf_counter() - t1) / args.steps
+    finally:
+        pkg.demag_destroy(plan)
+    return t_field, _stage_table(stage_bytes(n), stages, args.steps), nch
+
+
 def large_film_bench(pkg, args):
-    """demag_field on 1024x1024x32 cells of 4 nm, seeded random unit M x Ms."""
+    """demag_field on 1024x1024x32 cells of 4 nm, seeded random unit M x Ms, in
+    the FP32 form (the reported value) and in the two split-precision BF16 MFMA
+    forms; the MFMA results are compared with the FP32 result."""
     import torch
     import workloads as W
     cfg = W.LARGE_FILM
     n, cell = cfg["n"], cfg["cell"]
     cells = n[0] * n[1] * n[2]
     stream = torch.cuda.current_stream()
-    print("large film: set-up", file=sys.stderr, flush=True)
-    plan = pkg.demag_setup(n + cell, stream=stream)
-    pkg.demag_autotune(plan, stream)
-    nch = pkg.demag_get_chunks(plan)
-    print("large film: timing", file=sys.stderr, flush=True)
     M = torch.from_numpy(W.magnetisation(n, 0)).cuda()
+    H32 = torch.empty_like(M)
     H = torch.empty_like(M)
-    for _ in range(args.warmup):
-        pkg.demag_field(plan, M, H, stream)
+    b5 = sum(v for k, v in stage_bytes(n).items() if k != "llg")
+    modes = {}
+    for flags, name in ((0, "fp32"), (pkg.DEMAG_BF16X2_MFMA, "bf16x2_mfma"),
+                        (pkg.DEMAG_BF16X3_MFMA, "bf16x3_mfma")):
+        t_field, per_stage, nch = _field_run(pkg, n, cell, flags, M, H32 if flags == 0 else H,
+                                             args, stream, f"large film {name}")
+        entry = {"Gcells_per_s": round(cells / t_field / 1e9, 3), "ms_per_eval": round(1e3 * t_field, 4),
+                 "effective_hbm_frac": round(b5 / t_field / 1e9 / HBM_PEAK_GBS, 4),
+                 "yz_chunks": nch, "stages": per_stage}
+        if flags:
+            d = [float((H[a] - H32[a]).norm() / H32[a].norm()) for a in range(3)]
+            entry["rel_l2_vs_fp32_per_field"] = [float("%.3e" % v) for v in d]
+        modes[name] = entry
+    fp = modes["fp32"]
+    per_stage = fp["stages"]
+    dom = max(per_stage, key=lambda k: per_stage[k]["avg_us"] * per_stage[k]["launches"])
+    out = {"metric": "demag H_d evals: Gcells/s + % HBM roofline", "value": fp["Gcells_per_s"],
+           "unit": "Gcells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": fp["ms_per_eval"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": cfg["name"], "mesh": list(n), "yz_chunks": fp["yz_chunks"]},
+           "roofline": {"bound": "hbm", "kernel": dom, "achieved": per_stage[dom]["GB_per_s"],
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(per_stage[dom]["GB_per_s"] / HBM_PEAK_GBS, 4), "traffic": None},
+           "modes": modes}
+    return out
+
+
+def atomistic_bench(pkg, args):
+    """Heun steps of 1024x1024x256 spins (a = 0.4 nm, J = 1e-21 J, mu_s = 1 muB,
+    alpha = 0.05, dt = 1e-15 s, T = 0), demag on 4^3-spin macrocells."""
+    import torch
+    import workloads as W
+    cfg = W.ATOMISTIC
+    n = cfg["n"]
+    spins = n[0] * n[1] * n[2]
+    stream = torch.cuda.current_stream()
+    plan = pkg.atom_setup((n[0], n[1], n[2], cfg["a"], cfg["macro"]), stream=stream)
+    S = torch.from_numpy(W.unit_vectors((n[2], n[1], n[0]), seed=0)).cuda()
+    prm = (cfg["J"], cfg["mu_s"], cfg["alpha"], 2.21276e5, (0.0, 0.0, 0.0))
+    pkg.atom_step(plan, S, prm, cfg["dt"], args.warmup, stream)
     torch.cuda.synchronize()
-    pkg.demag_timing_enable(plan, args.steps * nch)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        pkg.demag_field(plan, M, H, stream)
+    pkg.atom_step(plan, S, prm, cfg["dt"], args.steps, stream)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    pkg.atom_destroy(plan)
+    norm_err = float((S.norm(dim=0) - 1).abs().max())
+    # Heun step bytes: 2 macro averages (12 B/spin each), predictor (read 12, write 24),
+    # corrector (read 36, write 12); neighbour re-reads come from cache
+    per_spin = 2 * 12 + 36 + 48
+    ms = 1e3 * el / args.steps
+    return {"metric": "atomistic spin-steps/s", "value": round(spins * args.steps / el / 1e9, 3),
+            "unit": "Gspin-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": cfg["name"], "lattice": list(n), "macro": cfg["macro"]},
+            "roofline": {"bound": "hbm", "kernel": "whole Heun step", "achieved":
+                         round(per_spin * spins / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(per_spin * spins / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic": None},
+            "max_norm_error": norm_err}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the short serving sample")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
+                    help="first run one plain device copy of MB megabytes (a known-size "
+                         "reference for hardware byte counters)")
+    ap.add_argument("--workload", default="thin_film", choices=("thin_film", "large_film", "atomistic"),
+                    help="thin_film (default): 512x512x16 RK4 LLG; large_film: 1024x1024x32 "
+                         "demag_field; atomistic: 1024x1024x256 spins, Heun, 4^3 macrocells")
+    ap.add_argument("--variants", type=lambda s: [int(v) for v in s.split(",")], default=None,
+                    help="pin the tile variant of the five FFT stages (e.g. 1,1,1,1,1) instead "
+                         "of autotuning")
+    ap.add_argument("--chunks", type=int, default=0,
+                    help="pin the number of chunks the y/z stages run in instead of autotuning")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="only the full serving workload: 256 requests x 1000 RK4 steps, "
+                         "Poisson loads 0.5/0.8/0.95 of the closed-loop throughput")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2308_08447_amd as pkg
+    import workloads as W
+
+    if args.copy_probe:
+        src = torch.empty(args.copy_probe * 2**20 // 4, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    if args.serve_full:
+        res = serve_bench(pkg, 256, 1000, (0.5, 0.8, 0.95))
+        print(json.dumps({"metric": "serve p50/p99 latency", "data": "synthetic",
+                          "config": {"workload": "serving: 256 LLG relaxations, meshes "
+                                     "{32..512}^2 x {1,2,4,8}, 1000 RK4 steps each"},
+                          "serve": res}), flush=True)
+        return
+
+    if args.workload == "large_film":
+        print(json.dumps(large_film_bench(pkg, args)), flush=True)
+        return
+    if args.workload == "atomistic":
+        print(json.dumps(atomistic_bench(pkg, args)), flush=True)
+        return
+
+    cfg = W.THIN_FILM
+    n, cell = cfg["n"], cfg["cell"]
+    cells = n[0] * n[1] * n[2]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    plan = pkg.demag_setup(n + cell, stream=stream)
+    if args.variants or args.chunks:
+        for st, v in enumerate(args.variants or []):
+            pkg.demag_set_variant(plan, st, v)
+        if args.chunks:
+            pkg.demag_set_chunks(plan, args.chunks)
+    else:
+        pkg.demag_autotune(plan, stream)
+    variants = [pkg.demag_get_variant(plan, st) for st in range(5)]
+    m0 = torch.from_numpy(W.unit_vectors((n[2], n[1], n[0]), seed=0)).to(dev)
+    m = m0.clone()
+    params = (cfg["Ms"], cfg["A"], cfg["alpha"], 2.21276e5, (0.0, 0.0, 0.0))
+
+    for _ in range(args.warmup):
+        pkg.llg_step(plan, m, params, cfg["dt"], 1, stream)
+    torch.cuda.synchronize()
+    nch = pkg.demag_get_chunks(plan)
+    pkg.demag_timing_enable(plan, 4 * args.steps * nch)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pkg.llg_step(plan, m, params, cfg["dt"], 1, stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
     stages = pkg.demag_timing_read(plan)
     pkg.demag_timing_enable(plan, 0)
-    # untimed: the same field without events, and a sampled check against the oracle
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
+
+    # standalone demag_field throughput (not the headline; same stream, no events)
+    M = (m0 * cfg["Ms"]).contiguous()
+    H = torch.empty_like(M)
+    for _ in range(3):
         pkg.demag_field(plan, M, H, stream)
     torch.cuda.synchronize()
-    t_field = (time.perf_counter() - t1) / args.steps
+    reps = 4 * args.steps
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        pkg.demag_field(plan, M, H, stream)
+    torch.cuda.synchronize()
+    t_field = (time.perf_counter() - t1) / reps
     pkg.demag_destroy(plan)
-    nbytes = stage_bytes(n)
-    per_stage = _stage_table(nbytes, stages, args.steps)
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = 4 * cells * args.steps / elapsed / 1e9
+    nbytes = stage_bytes(n)   # per H_d evaluation (per RK stage for "llg")
+    evals = 4 * args.steps
+    per_stage = _stage_table(nbytes, stages, evals)
     dom = max(per_stage, key=lambda k: per_stage[k]["avg_us"] * per_stage[k]["launches"])
     b5 = sum(v for k, v in nbytes.items() if k != "llg")
     out = {"metric": "demag H_d evals: Gcells/s + % HBM roofline", "value": round(cells / t_field / 1e9, 3),
@@ -249,6 +462,11 @@ def main():
     ap.add_argument("--workload", default="thin_film", choices=("thin_film", "large_film", "atomistic"),
                     help="thin_film (default): 512x512x16 RK4 LLG; large_film: 1024x1024x32 "
                          "demag_field; atomistic: 1024x1024x256 spins, Heun, 4^3 macrocells")
+    ap.add_argument("--variants", type=lambda s: [int(v) for v in s.split(",")], default=None,
+                    help="pin the tile variant of the five FFT stages (e.g. 1,1,1,1,1) instead "
+                         "of autotuning")
+    ap.add_argument("--chunks", type=int, default=0,
+                    help="pin the number of chunks the y/z stages run in instead of autotuning")
     ap.add_argument("--serve-full", action="store_true",
                     help="only the full serving workload: 256 requests x 1000 RK4 steps, "
                          "Poisson loads 0.5/0.8/0.95 of the closed-loop throughput")
@@ -291,7 +509,13 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     plan = pkg.demag_setup(n + cell, stream=stream)
-    pkg.demag_autotune(plan, stream)
+    if args.variants or args.chunks:
+        for st, v in enumerate(args.variants or []):
+            pkg.demag_set_variant(plan, st, v)
+        if args.chunks:
+            pkg.demag_set_chunks(plan, args.chunks)
+    else:
+        pkg.demag_autotune(plan, stream)
     variants = [pkg.demag_get_variant(plan, st) for st in range(5)]
     m0 = torch.from_numpy(W.unit_vectors((n[2], n[1], n[0]), seed=0)).to(dev)
     m = m0.clone()
@@ -362,7 +586,8 @@ def main():
                    "stage_variants": variants, "yz_chunks": nch},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": counter_traffic(dom),
+                     "bytes_per_launch": per_stage[dom]["bytes_per_launch"]},
         "stages": per_stage,
         "demag_field_gcells_per_s": round(cells / t_field / 1e9, 3),
         "demag_field_us": round(1e6 * t_field, 1),

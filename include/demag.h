@@ -48,7 +48,16 @@ enum {
 
 /* ---- plan flags --------------------------------------------------------- */
 enum {
-    DEMAG_FP32 = 0            /* FP32 FFT stages (default) */
+    DEMAG_FP32 = 0,           /* FP32 FFT stages (default) */
+    /* The radix-16 passes of every FFT stage as BF16 matrix products on the
+     * matrix cores: each 16-point DFT of a batch of 32 is one real 32x32 DFT
+     * matrix times the 32 x 32 block of input real/imaginary parts, both
+     * split into BF16 terms (v = v0 + v1 [+ v2]) and the leading cross
+     * products accumulated in FP32; twiddles, passes of radix < 16, the
+     * tensor product and all data stay FP32.  Same result definition and
+     * tolerance as DEMAG_FP32. */
+    DEMAG_BF16X2_MFMA = 1,    /* two-term split, 3 products per DFT step */
+    DEMAG_BF16X3_MFMA = 2     /* three-term split, 6 products per DFT step */
 };
 
 /* Mesh of n_x x n_y x n_z rectangular cells of size dx x dy x dz (m). */
@@ -66,7 +75,7 @@ typedef struct demag_plan demag_plan;   /* opaque; owns N^ and the FFT workspace
  * real components in FP32 packed by the y and z symmetries, and allocates the
  * FFT workspace.
  *   mesh    in   mesh description (copied).
- *   flags   in   DEMAG_FP32.
+ *   flags   in   DEMAG_FP32, DEMAG_BF16X2_MFMA or DEMAG_BF16X3_MFMA (one of them).
  *   stream  in   hipStream_t used for the set-up kernels; the call synchronises it.
  *   out     out  receives the new plan (NULL on failure).
  * Errors: EINVAL (null/invalid mesh), EUNSUPPORTED (size), ENOMEM, EHIP.
@@ -186,6 +195,8 @@ int demag_timing_read(demag_plan* plan, double* total_ms, int32_t* launches);
  * demag_autotune times every variant of every stage on the plan's own buffers
  * (HIP events, 5 launches each; synchronises `stream`), keeps the fastest and
  * remembers the choice for later plans of the same mesh size in this process.
+ * Plans made with a BF16 MFMA flag always run the middle tile shape (variant
+ * 1, whatever is set); demag_autotune then tunes only the chunk count.
  */
 enum { DEMAG_NVARIANTS = 3 };
 int demag_autotune(demag_plan* plan, void* stream);

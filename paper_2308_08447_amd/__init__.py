@@ -22,6 +22,8 @@ DEMAG_EUNSUPPORTED = -3
 DEMAG_EHIP = -4
 DEMAG_EBUSY = -5
 DEMAG_FP32 = 0
+DEMAG_BF16X2_MFMA = 1   # radix-16 passes as 2-term split BF16 MFMA products
+DEMAG_BF16X3_MFMA = 2   # 3-term split
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EUNSUPPORTED", -4: "EHIP", -5: "EBUSY"}
 

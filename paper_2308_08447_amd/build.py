@@ -13,7 +13,8 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdemag.so")
-SOURCES = ["capi.hip", "stages.hip", "tensor.hip", "dynamics.hip", "serve.hip"]
+SOURCES = ["capi.hip", "stages_x.hip", "stages_y.hip", "stages_z.hip", "tensor.hip", "dynamics.hip",
+           "serve.hip"]
 ARCH = os.environ.get("DEMAG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -26,6 +27,7 @@ FLAGS = [
     "-ffp-contract=off",
     "-Wno-unused-command-line-argument",
 ]
+FLAGS_OBJ = [f for f in FLAGS if f != "-shared"]
 
 
 def hipcc():
@@ -35,20 +37,30 @@ def hipcc():
     raise RuntimeError("hipcc not found (ROCm is required to build the HIP library)")
 
 
-def build(verbose=False):
-    """Compile every source in one hipcc invocation; returns the library path."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    fd, tmp = tempfile.mkstemp(suffix=".so", dir=HERE)
-    os.close(fd)
-    cmd = [hipcc()] + FLAGS + ["-I", os.path.join(HERE, "..", "include")] + srcs + ["-o", tmp]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        os.unlink(tmp)
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed with status {res.returncode}")
-    os.replace(tmp, LIB)
+        raise RuntimeError(f"hipcc failed with status {res.returncode}: {' '.join(cmd)}")
+
+
+def build(verbose=False):
+    """Compile every source to an object in parallel, then link; returns the library path."""
+    from concurrent.futures import ThreadPoolExecutor
+    inc = ["-I", os.path.join(HERE, "..", "include")]
+    with tempfile.TemporaryDirectory(dir=HERE, prefix="_build") as tmpd:
+        objs = [os.path.join(tmpd, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        cmds = [[hipcc()] + FLAGS_OBJ + inc + ["-c", os.path.join(CSRC, s), "-o", o]
+                for s, o in zip(SOURCES, objs)]
+        jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+        with ThreadPoolExecutor(jobs) as ex:
+            for f in [ex.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        out = os.path.join(tmpd, "libdemag.so")
+        _run([hipcc(), "-shared", f"--offload-arch={ARCH}"] + objs + ["-o", out], verbose)
+        os.replace(out, LIB)
     return LIB
 
 

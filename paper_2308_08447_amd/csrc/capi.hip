@@ -162,7 +162,7 @@ struct Tuned {
 };
 // Variants picked by demag_autotune, shared by later plans of the same mesh size.
 static std::mutex g_tune_mu;
-static std::map<std::array<int, 3>, Tuned> g_tuned;
+static std::map<std::array<int, 4>, Tuned> g_tuned;
 
 static void free_timing(demag_plan* p) {
     for (int s = 0; s < DEMAG_NSTAGES; ++s) {
@@ -194,6 +194,7 @@ int create_plan(const demag_mesh* mesh, uint32_t flags, hipStream_t s, demag_pla
     p->dy = mesh->dy;
     p->dz = mesh->dz;
     p->flags = flags;
+    p->mf = (flags & DEMAG_BF16X3_MFMA) ? 3 : (flags & DEMAG_BF16X2_MFMA) ? 2 : 0;
     (void)hipGetDevice(&p->device);
     auto bail = [&](int code) {
         free_plan(p);
@@ -212,7 +213,7 @@ int create_plan(const demag_mesh* mesh, uint32_t flags, hipStream_t s, demag_pla
     if ((rc = get_spectrum(g, mesh->dx, mesh->dy, mesh->dz, s, &p->spec))) return bail(rc);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tuned.find({g.nx, g.ny, g.nz});
+        auto it = g_tuned.find({g.nx, g.ny, g.nz, p->mf});
         if (it != g_tuned.end()) {
             for (int i = 0; i < 5; ++i) p->variant[i] = it->second.variant[i];
             p->nch = it->second.nch;
@@ -268,31 +269,31 @@ static int run_field_single(demag_plan* p, const float* M, float* H, float scale
     int rc;
     {
         StageTimer t(p, DEMAG_STAGE_X_FWD, s);
-        if ((rc = launch_x_forward(one(xdesc(p, M, H, scale)), g.nx, p->variant[0], p->tw, s))) return rc;
+        if ((rc = launch_x_forward(one(xdesc(p, M, H, scale)), g.nx, p->variant[0], p->mf, p->tw, s))) return rc;
     }
     if (g.ny == 1) {
         StageTimer t(p, DEMAG_STAGE_Z_CONV, s);
-        if ((rc = launch_z_convolve(one(zdesc(p, 0, g.X1)), g.Nz, p->variant[2], p->tw, s))) return rc;
+        if ((rc = launch_z_convolve(one(zdesc(p, 0, g.X1)), g.Nz, p->variant[2], p->mf, p->tw, s))) return rc;
     } else {
         const int per = (g.X1 + p->nch - 1) / p->nch;
         for (int k0 = 0; k0 < g.X1; k0 += per) {
             const int nk = per < g.X1 - k0 ? per : g.X1 - k0;
             {
                 StageTimer t(p, DEMAG_STAGE_Y_FWD, s);
-                if ((rc = launch_y_forward(one(ydesc(p, k0, nk)), g.ny, p->variant[1], p->tw, s))) return rc;
+                if ((rc = launch_y_forward(one(ydesc(p, k0, nk)), g.ny, p->variant[1], p->mf, p->tw, s))) return rc;
             }
             {
                 StageTimer t(p, DEMAG_STAGE_Z_CONV, s);
-                if ((rc = launch_z_convolve(one(zdesc(p, k0, nk)), g.Nz, p->variant[2], p->tw, s))) return rc;
+                if ((rc = launch_z_convolve(one(zdesc(p, k0, nk)), g.Nz, p->variant[2], p->mf, p->tw, s))) return rc;
             }
             {
                 StageTimer t(p, DEMAG_STAGE_Y_INV, s);
-                if ((rc = launch_y_inverse(one(ydesc(p, k0, nk)), g.ny, p->variant[3], p->tw, s))) return rc;
+                if ((rc = launch_y_inverse(one(ydesc(p, k0, nk)), g.ny, p->variant[3], p->mf, p->tw, s))) return rc;
             }
         }
     }
     StageTimer t(p, DEMAG_STAGE_X_INV, s);
-    return launch_x_inverse(one(xdesc(p, M, H, scale)), g.nx, p->variant[4], p->tw, s);
+    return launch_x_inverse(one(xdesc(p, M, H, scale)), g.nx, p->variant[4], p->mf, p->tw, s);
 }
 
 // Groups item indices by a key, keeping first-appearance order, in runs of at most MAXB.
@@ -328,41 +329,41 @@ int run_fields(demag_plan* const* plans, const float* const* M, float* const* H,
     }
     if (items.empty()) return DEMAG_OK;
     const float2* tw = plans[items[0]]->tw;
-    auto by_nx = groups(items, [&](int i) { return plans[i]->g.nx; });
+    auto by_nx = groups(items, [&](int i) { return plans[i]->g.nx * 8LL + plans[i]->mf; });
     std::vector<int> yitems;
     for (int i : items)
         if (plans[i]->g.ny > 1) yitems.push_back(i);
-    auto by_ny = groups(yitems, [&](int i) { return plans[i]->g.ny; });
-    auto by_nz = groups(items, [&](int i) { return plans[i]->g.Nz; });
+    auto by_ny = groups(yitems, [&](int i) { return plans[i]->g.ny * 8LL + plans[i]->mf; });
+    auto by_nz = groups(items, [&](int i) { return plans[i]->g.Nz * 8LL + plans[i]->mf; });
     for (auto& grp : by_nx) {
         XBatch b;
         b.count = (int)grp.size();
         for (int r = 0; r < b.count; ++r) b.d[r] = xdesc(plans[grp[r]], M[grp[r]], H[grp[r]], scale[grp[r]]);
-        if ((rc = launch_x_forward(b, plans[grp[0]]->g.nx, plans[grp[0]]->variant[0], tw, s))) return rc;
+        if ((rc = launch_x_forward(b, plans[grp[0]]->g.nx, plans[grp[0]]->variant[0], plans[grp[0]]->mf, tw, s))) return rc;
     }
     for (auto& grp : by_ny) {
         YBatch b;
         b.count = (int)grp.size();
         for (int r = 0; r < b.count; ++r) b.d[r] = ydesc(plans[grp[r]], 0, plans[grp[r]]->g.X1);
-        if ((rc = launch_y_forward(b, plans[grp[0]]->g.ny, plans[grp[0]]->variant[1], tw, s))) return rc;
+        if ((rc = launch_y_forward(b, plans[grp[0]]->g.ny, plans[grp[0]]->variant[1], plans[grp[0]]->mf, tw, s))) return rc;
     }
     for (auto& grp : by_nz) {
         ZBatch b;
         b.count = (int)grp.size();
         for (int r = 0; r < b.count; ++r) b.d[r] = zdesc(plans[grp[r]], 0, plans[grp[r]]->g.X1);
-        if ((rc = launch_z_convolve(b, plans[grp[0]]->g.Nz, plans[grp[0]]->variant[2], tw, s))) return rc;
+        if ((rc = launch_z_convolve(b, plans[grp[0]]->g.Nz, plans[grp[0]]->variant[2], plans[grp[0]]->mf, tw, s))) return rc;
     }
     for (auto& grp : by_ny) {
         YBatch b;
         b.count = (int)grp.size();
         for (int r = 0; r < b.count; ++r) b.d[r] = ydesc(plans[grp[r]], 0, plans[grp[r]]->g.X1);
-        if ((rc = launch_y_inverse(b, plans[grp[0]]->g.ny, plans[grp[0]]->variant[3], tw, s))) return rc;
+        if ((rc = launch_y_inverse(b, plans[grp[0]]->g.ny, plans[grp[0]]->variant[3], plans[grp[0]]->mf, tw, s))) return rc;
     }
     for (auto& grp : by_nx) {
         XBatch b;
         b.count = (int)grp.size();
         for (int r = 0; r < b.count; ++r) b.d[r] = xdesc(plans[grp[r]], M[grp[r]], H[grp[r]], scale[grp[r]]);
-        if ((rc = launch_x_inverse(b, plans[grp[0]]->g.nx, plans[grp[0]]->variant[4], tw, s))) return rc;
+        if ((rc = launch_x_inverse(b, plans[grp[0]]->g.nx, plans[grp[0]]->variant[4], plans[grp[0]]->mf, tw, s))) return rc;
     }
     return DEMAG_OK;
 }
@@ -454,13 +455,17 @@ struct atom_plan {
     float* f0 = nullptr;    // predictor slope (3 N)
 };
 
+static bool valid_flags(uint32_t flags) {
+    return flags == DEMAG_FP32 || flags == DEMAG_BF16X2_MFMA || flags == DEMAG_BF16X3_MFMA;
+}
+
 extern "C" {
 
 const char* demag_last_error(void) { return g_last_error.c_str(); }
 
 size_t demag_plan_bytes(const demag_mesh* mesh, uint32_t flags) {
     Geometry g;
-    if (flags != DEMAG_FP32) return 0;
+    if (!valid_flags(flags)) return 0;
     if (check_mesh(mesh, &g) != DEMAG_OK) return 0;
     return g.k_elems() * sizeof(float) + workspace_bytes(g);
 }
@@ -468,7 +473,7 @@ size_t demag_plan_bytes(const demag_mesh* mesh, uint32_t flags) {
 int demag_setup(const demag_mesh* mesh, uint32_t flags, void* stream, demag_plan** out) {
     if (!out) return fail(DEMAG_EINVAL, "out is NULL");
     *out = nullptr;
-    if (flags != DEMAG_FP32) {
+    if (!valid_flags(flags)) {
         Geometry g;
         int rc = check_mesh(mesh, &g);
         if (rc) return rc;
@@ -580,10 +585,11 @@ int demag_autotune(demag_plan* plan, void* stream) {
         *ms_out = ms;
         return DEMAG_OK;
     };
-    // 1. tile variants, stage by stage, on the first chunk
+    // 1. tile variants, stage by stage, on the first chunk (the MFMA forms exist
+    //    in one tile shape only)
     rc = run_field_single(plan, M, H, 1.0f, s);
     const int per = (g.X1 + plan->nch - 1) / plan->nch;
-    for (int st = 0; st < 5 && !rc; ++st) {
+    for (int st = 0; st < 5 && !rc && plan->mf == 0; ++st) {
         if ((st == 1 || st == 3) && g.ny == 1) continue;
         double best = 1e30;
         int best_v = plan->variant[st];
@@ -591,11 +597,11 @@ int demag_autotune(demag_plan* plan, void* stream) {
             const int nk = g.ny == 1 ? g.X1 : per;
             auto fn = [&]() -> int {
                 switch (st) {
-                    case 0: return launch_x_forward(one(xdesc(plan, M, H, 1.0f)), g.nx, v, plan->tw, s);
-                    case 1: return launch_y_forward(one(ydesc(plan, 0, nk)), g.ny, v, plan->tw, s);
-                    case 2: return launch_z_convolve(one(zdesc(plan, 0, nk)), g.Nz, v, plan->tw, s);
-                    case 3: return launch_y_inverse(one(ydesc(plan, 0, nk)), g.ny, v, plan->tw, s);
-                    default: return launch_x_inverse(one(xdesc(plan, M, H, 1.0f)), g.nx, v, plan->tw, s);
+                    case 0: return launch_x_forward(one(xdesc(plan, M, H, 1.0f)), g.nx, v, plan->mf, plan->tw, s);
+                    case 1: return launch_y_forward(one(ydesc(plan, 0, nk)), g.ny, v, plan->mf, plan->tw, s);
+                    case 2: return launch_z_convolve(one(zdesc(plan, 0, nk)), g.Nz, v, plan->mf, plan->tw, s);
+                    case 3: return launch_y_inverse(one(ydesc(plan, 0, nk)), g.ny, v, plan->mf, plan->tw, s);
+                    default: return launch_x_inverse(one(xdesc(plan, M, H, 1.0f)), g.nx, v, plan->mf, plan->tw, s);
                 }
             };
             double ms = 0.0;
@@ -630,7 +636,7 @@ int demag_autotune(demag_plan* plan, void* stream) {
     Tuned t;
     for (int i = 0; i < 5; ++i) t.variant[i] = plan->variant[i];
     t.nch = plan->nch;
-    g_tuned[{g.nx, g.ny, g.nz}] = t;
+    g_tuned[{g.nx, g.ny, g.nz, plan->mf}] = t;
     return DEMAG_OK;
 }
 

@@ -72,11 +72,11 @@ using XBatch = StageBatch<XDesc>;
 using YBatch = StageBatch<YDesc>;
 using ZBatch = StageBatch<ZDesc>;
 
-int launch_x_forward(XBatch b, int nx, int variant, const float2* tw, hipStream_t s);
-int launch_x_inverse(XBatch b, int nx, int variant, const float2* tw, hipStream_t s);
-int launch_y_forward(YBatch b, int ny, int variant, const float2* tw, hipStream_t s);
-int launch_y_inverse(YBatch b, int ny, int variant, const float2* tw, hipStream_t s);
-int launch_z_convolve(ZBatch b, int Nz, int variant, const float2* tw, hipStream_t s);
+int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hipStream_t s);
+int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hipStream_t s);
+int launch_y_forward(YBatch b, int ny, int variant, int mf, const float2* tw, hipStream_t s);
+int launch_y_inverse(YBatch b, int ny, int variant, int mf, const float2* tw, hipStream_t s);
+int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, hipStream_t s);
 // Largest transform length the twiddle table must hold for this geometry.
 int twiddle_table_length(const Geometry& g);
 // Fills the host table (2 * Lmax float2) with exp(-2 pi i t/L) at offset L.

@@ -15,6 +15,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "mfma_dft.h"
+
 namespace dm {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -93,6 +95,20 @@ constexpr int radix_of(int L, int p) {
     return 1 << (base + (p < extra ? 1 : 0));
 }
 constexpr int npasses(int L) { return (ilog2c(L) + 3) / 4; }
+
+// Radix plan of the split-precision MFMA transforms (MF > 0): every pass is
+// radix 16 except a first pass that takes the remaining 2, 4 or 8 (e.g. 2048 =
+// 8*16*16); the pass count is the same as above.
+template <int MF>
+constexpr int radix_at(int L, int p) {
+    if constexpr (MF == 0) {
+        return radix_of(L, p);
+    } else {
+        int k = ilog2c(L), rem = k % 4;
+        if (k <= 4) return L;
+        return (p == 0 && rem != 0) ? (1 << rem) : 16;
+    }
+}
 
 // LDS index padding: one float2 of padding every 16 elements breaks the
 // power-of-two strides of the Stockham writes across banks.
@@ -257,12 +273,209 @@ __device__ __forceinline__ void last_pass(float2* buf, const float2* __restrict_
     }
 }
 
-template <int L, int P, int NS, int DIR, int NLINES, int NT, class Addr>
-__device__ __forceinline__ void middle_passes(float2* buf, const float2* __restrict__ tw) {
+// ---- radix-16 passes on the matrix cores (split-precision BF16, see mfma_dft.h)
+// The pass's butterflies are taken 32 at a time by one wave: butterfly
+// b = 32 g + n sits in lanes n and n + 32, lane half h holding inputs and
+// outputs 8h .. 8h+7 / out_index(h, .).  Batches g are dealt to the NT/64 waves
+// round-robin; the batch loop condition is uniform across a wave, so every lane
+// reaches each MFMA, and lanes past the last butterfly carry zeros.
+template <int TOT, int NT>
+struct MfSched {
+    static constexpr int NW = NT / 64;
+    static constexpr int NG = (TOT + 31) / 32;
+    static constexpr int GPW = (NG + NW - 1) / NW;
+};
+
+template <int L, int NS, int DIR, int NLINES, int NT, class Addr, int MF>
+__device__ __forceinline__ void mf_stockham_pass(float2* buf, const float2* __restrict__ tw,
+                                                 const Dft16Matrix<MF>& F) {
+    constexpr int NB = L / 16;
+    constexpr int TOT = NB * NLINES;
+    using S = MfSched<TOT, NT>;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
+    float2 y[S::GPW][8];
+#pragma unroll
+    for (int q = 0; q < S::GPW; ++q) {
+        const int g = w + q * S::NW;
+        if (S::NG % S::NW == 0 || g < S::NG) {
+            const int b = 32 * g + n;
+            float2 x[8];
+            if (TOT % 32 == 0 || b < TOT) {
+                int line, j;
+                Addr::template split<NB>(b, line, j);
+                const int k = j % NS;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int r = 8 * h + c;
+                    x[c] = buf[Addr::idx(line, j + r * NB)];
+                    if (NS > 1 && r > 0) {
+                        float2 tv = tw[k * r * (L / (NS * 16))];
+                        if constexpr (DIR > 0) tv.y = -tv.y;
+                        x[c] = cmul(x[c], tv);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) x[c] = make_float2(0.f, 0.f);
+            }
+            mfma_dft16<MF>(F, x, y[q]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < S::GPW; ++q) {
+        const int g = w + q * S::NW;
+        const int b = 32 * g + n;
+        if ((S::NG % S::NW == 0 || g < S::NG) && (TOT % 32 == 0 || b < TOT)) {
+            int line, j;
+            Addr::template split<NB>(b, line, j);
+            const int k = j % NS;
+            const int base = (j / NS) * NS * 16 + k;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) buf[Addr::idx(line, base + out_index(h, c) * NS)] = y[q][c];
+        }
+    }
+    __syncthreads();
+}
+
+// First pass (sub-size 1, no twiddles) reading its inputs through src.
+template <int L, int DIR, int NLINES, int NT, class Addr, bool HALF_IN, bool SYNC_IO, int MF,
+          class Src>
+__device__ __forceinline__ void mf_first_pass(float2* buf, Src& src, const Dft16Matrix<MF>& F) {
+    constexpr int NB = L / 16;
+    constexpr int TOT = NB * NLINES;
+    using S = MfSched<TOT, NT>;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
+    float2 x[S::GPW][8];
+#pragma unroll
+    for (int q = 0; q < S::GPW; ++q) {
+        const int g = w + q * S::NW;
+        const int b = 32 * g + n;
+        const bool live = (S::NG % S::NW == 0 || g < S::NG) && (TOT % 32 == 0 || b < TOT);
+        int line = 0, j = 0;
+        if (live) Addr::template split<NB>(b, line, j);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int r = 8 * h + c;
+            x[q][c] = (live && !(HALF_IN && h == 1)) ? src(line, j + r * NB) : make_float2(0.f, 0.f);
+        }
+    }
+    if constexpr (SYNC_IO) __syncthreads();
+#pragma unroll
+    for (int q = 0; q < S::GPW; ++q) {
+        const int g = w + q * S::NW;
+        if (S::NG % S::NW == 0 || g < S::NG) {
+            float2 y[8];
+            mfma_dft16<MF>(F, x[q], y);
+            const int b = 32 * g + n;
+            if (TOT % 32 == 0 || b < TOT) {
+                int line, j;
+                Addr::template split<NB>(b, line, j);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) buf[Addr::idx(line, j * 16 + out_index(h, c))] = y[c];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Last pass (sub-size L/16) handing its outputs to sink.
+template <int L, int DIR, int NLINES, int NT, class Addr, bool HALF_OUT, bool SYNC_IO, int MF,
+          class Sink>
+__device__ __forceinline__ void mf_last_pass(float2* buf, const float2* __restrict__ tw, Sink& sink,
+                                             const Dft16Matrix<MF>& F) {
+    constexpr int NB = L / 16;  // == sub-size of this pass
+    constexpr int TOT = NB * NLINES;
+    using S = MfSched<TOT, NT>;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
+    float2 x[S::GPW][8];
+#pragma unroll
+    for (int q = 0; q < S::GPW; ++q) {
+        const int g = w + q * S::NW;
+        const int b = 32 * g + n;
+        const bool live = (S::NG % S::NW == 0 || g < S::NG) && (TOT % 32 == 0 || b < TOT);
+        int line = 0, j = 0;
+        if (live) Addr::template split<NB>(b, line, j);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int r = 8 * h + c;
+            x[q][c] = live ? buf[Addr::idx(line, j + r * NB)] : make_float2(0.f, 0.f);
+            if (live && r > 0) {
+                float2 tv = tw[j * r];
+                if constexpr (DIR > 0) tv.y = -tv.y;
+                x[q][c] = cmul(x[q][c], tv);
+            }
+        }
+    }
+    if constexpr (SYNC_IO) __syncthreads();
+#pragma unroll
+    for (int q = 0; q < S::GPW; ++q) {
+        const int g = w + q * S::NW;
+        if (S::NG % S::NW == 0 || g < S::NG) {
+            float2 y[8];
+            mfma_dft16<MF>(F, x[q], y);
+            const int b = 32 * g + n;
+            if (TOT % 32 == 0 || b < TOT) {
+                int line, j;
+                Addr::template split<NB>(b, line, j);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int m = out_index(h, c);
+                    if (!HALF_OUT || m < 8) sink(line, j + m * NB, y[c]);
+                }
+            }
+        }
+    }
+}
+
+// L == 16: the whole transform as one batch of matrix products, src -> sink.
+template <int DIR, int NLINES, int NT, class Addr, bool HALF_IN, bool HALF_OUT, bool SYNC_IO,
+          int MF, class Src, class Sink>
+__device__ __forceinline__ void mf_single_pass(Src& src, Sink& sink, const Dft16Matrix<MF>& F) {
+    constexpr int TOT = NLINES;
+    using S = MfSched<TOT, NT>;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
+    float2 x[S::GPW][8];
+#pragma unroll
+    for (int q = 0; q < S::GPW; ++q) {
+        const int g = w + q * S::NW;
+        const int b = 32 * g + n;
+        const bool live = (S::NG % S::NW == 0 || g < S::NG) && (TOT % 32 == 0 || b < TOT);
+        int line = 0, j = 0;
+        if (live) Addr::template split<1>(b, line, j);
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            x[q][c] = (live && !(HALF_IN && h == 1)) ? src(line, 8 * h + c) : make_float2(0.f, 0.f);
+    }
+    if constexpr (SYNC_IO) __syncthreads();
+#pragma unroll
+    for (int q = 0; q < S::GPW; ++q) {
+        const int g = w + q * S::NW;
+        if (S::NG % S::NW == 0 || g < S::NG) {
+            float2 y[8];
+            mfma_dft16<MF>(F, x[q], y);
+            const int b = 32 * g + n;
+            if (TOT % 32 == 0 || b < TOT) {
+                int line, j;
+                Addr::template split<1>(b, line, j);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int m = out_index(h, c);
+                    if (!HALF_OUT || m < 8) sink(line, m, y[c]);
+                }
+            }
+        }
+    }
+}
+
+template <int L, int P, int NS, int DIR, int NLINES, int NT, class Addr, int MF>
+__device__ __forceinline__ void middle_passes(float2* buf, const float2* __restrict__ tw,
+                                              const Dft16Matrix<MF>& F) {
     if constexpr (P < npasses(L) - 1) {
-        constexpr int R = radix_of(L, P);
-        stockham_pass<L, R, NS, DIR, NLINES, NT, Addr>(buf, tw);
-        middle_passes<L, P + 1, NS * R, DIR, NLINES, NT, Addr>(buf, tw);
+        constexpr int R = radix_at<MF>(L, P);
+        if constexpr (MF > 0 && R == 16) mf_stockham_pass<L, NS, DIR, NLINES, NT, Addr, MF>(buf, tw, F);
+        else stockham_pass<L, R, NS, DIR, NLINES, NT, Addr>(buf, tw);
+        middle_passes<L, P + 1, NS * R, DIR, NLINES, NT, Addr, MF>(buf, tw, F);
     }
 }
 
@@ -300,19 +513,34 @@ __device__ __forceinline__ void single_pass(Src& src, Sink& sink) {
     }
 }
 
+// MF selects the arithmetic of the radix-16 passes: 0 = FP32 butterflies on the
+// vector ALUs; 2 or 3 = the split-precision BF16 DFT-matrix products on MFMA
+// (see mfma_dft16).  Passes of radix < 16 always run in FP32.
 template <int L, int DIR, int NLINES, int NT, class Addr, bool HALF_IN, bool HALF_OUT,
-          bool SYNC_IO, class Src, class Sink>
+          bool SYNC_IO, int MF = 0, class Src, class Sink>
 __device__ __forceinline__ void fft_io(float2* buf, const float2* __restrict__ tw, Src src,
                                        Sink sink) {
     constexpr int P = npasses(L);
+    Dft16Matrix<MF> F;
+    if constexpr (MF > 0 && L >= 16) F.template init<DIR>();
     if constexpr (P <= 1) {
-        single_pass<L, DIR, NLINES, NT, Addr, HALF_IN, HALF_OUT, SYNC_IO>(src, sink);
+        if constexpr (MF > 0 && L == 16)
+            mf_single_pass<DIR, NLINES, NT, Addr, HALF_IN, HALF_OUT, SYNC_IO, MF>(src, sink, F);
+        else
+            single_pass<L, DIR, NLINES, NT, Addr, HALF_IN, HALF_OUT, SYNC_IO>(src, sink);
         return;
     } else {
-    constexpr int R0 = radix_of(L, 0);
-    first_pass<L, R0, DIR, NLINES, NT, Addr, HALF_IN, SYNC_IO, true>(buf, src);
-    middle_passes<L, 1, R0, DIR, NLINES, NT, Addr>(buf, tw);
-    last_pass<L, radix_of(L, P - 1), DIR, NLINES, NT, Addr, HALF_OUT, SYNC_IO>(buf, tw, sink);
+    constexpr int R0 = radix_at<MF>(L, 0);
+    if constexpr (MF > 0 && R0 == 16)
+        mf_first_pass<L, DIR, NLINES, NT, Addr, HALF_IN, SYNC_IO, MF>(buf, src, F);
+    else
+        first_pass<L, R0, DIR, NLINES, NT, Addr, HALF_IN, SYNC_IO, true>(buf, src);
+    middle_passes<L, 1, R0, DIR, NLINES, NT, Addr, MF>(buf, tw, F);
+    constexpr int RL = radix_at<MF>(L, P - 1);
+    if constexpr (MF > 0 && RL == 16)
+        mf_last_pass<L, DIR, NLINES, NT, Addr, HALF_OUT, SYNC_IO, MF>(buf, tw, sink, F);
+    else
+        last_pass<L, RL, DIR, NLINES, NT, Addr, HALF_OUT, SYNC_IO>(buf, tw, sink);
     }
 }
 

@@ -44,6 +44,7 @@ struct demag_plan {
     dm::Geometry g;
     double dx = 0, dy = 0, dz = 0;
     uint32_t flags = 0;
+    int mf = 0;             // radix-16 passes: 0 FP32, 2 / 3 BF16 split-precision MFMA (terms)
     const float2* tw = nullptr;
     float2* S1 = nullptr;
     float2* S2 = nullptr;   // chunk buffer of xc kx planes; == S1 (xc = X1) when ny == 1

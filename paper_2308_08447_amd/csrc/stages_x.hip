@@ -1,0 +1,221 @@
+// stages_x.hip -- x stages: R2C of packed real row pairs, C2R with the Hermitian combine (see stage_common.h for the stage order).
+#include "stage_common.h"
+
+namespace dm {
+
+// ============================================================================ x
+// One block: component c, plane z, rows y0 .. y0+TY-1 (TY/2 packed pairs).
+// Forward: each pair z = a + i b is transformed twice (even outputs: DFT of z,
+// odd outputs: DFT of z W_2L^t); the first pass reads the rows straight from M,
+// the last pass leaves the spectrum in LDS in natural order, from where the
+// Hermitian separation writes S1 transposed (consecutive threads, consecutive y).
+template <int L, int TY, int MF>
+__global__ __launch_bounds__(NT) void x_forward_kernel(const XBatch b,
+                                                       const float2* __restrict__ tw_all) {
+    constexpr int NP = TY / 2;
+    constexpr int LS = lpad_c(L) + 1;  // odd stride: the pairs of one frequency hit distinct banks
+    __shared__ float2 buf[NP * LS];
+    __shared__ float2 twL[L];
+    const float2* tw2L = tw_all + 2 * L;
+    stage_table(twL, tw_all + L, L);
+    const int tid = threadIdx.x;
+    const int gid = xcd_tile(blockIdx.x, gridDim.x);
+    const int item = batch_item(b, gid);
+    const float* __restrict__ M = b.d[item].M;
+    float2* __restrict__ S1 = b.d[item].S1;
+    const int ny = b.d[item].ny, nz = b.d[item].nz;
+    const float scale = b.d[item].scale;
+    const int nyt = (ny + TY - 1) / TY;
+    const int id = gid - b.start[item];
+    const int y0 = (id % nyt) * TY, z = (id / nyt) % nz, c = id / (nyt * nz);
+    const int rows = min(TY, ny - y0);
+    const float* src = M + ((size_t)(c * nz + z) * ny + y0) * L;
+    float2* dst = S1 + (size_t)(c * nz + z) * (L + 1) * ny + y0;
+
+    auto pair = [&](int p, int t) {
+        float a = (2 * p < rows) ? src[(size_t)(2 * p) * L + t] : 0.f;
+        float b = (2 * p + 1 < rows) ? src[(size_t)(2 * p + 1) * L + t] : 0.f;
+        return make_float2(a * scale, b * scale);
+    };
+    auto pair_odd = [&](int p, int t) { return cmul(pair(p, t), tw2L[t]); };
+    auto to_lds = [&](int p, int k, float2 v) { buf[p * LS + lpad(k)] = v; };
+    using Rows = RowLines<LS>;
+
+    fft_io<L, -1, NP, NT, Rows, false, false, true, MF>(buf, twL, pair, to_lds);
+    __syncthreads();
+    // even frequencies kx = 2m, m = 0..L/2: Z[2m] = E[m], Z[2L-2m] = E[(L-m) mod L]
+    for (int it = tid; it < (L / 2 + 1) * NP; it += NT) {
+        int p = it % NP, m = it / NP;
+        float2 Zk = buf[p * LS + lpad(m)];
+        float2 Zn = cconj(buf[p * LS + lpad((L - m) & (L - 1))]);
+        float2 Xa = cscale(cadd(Zk, Zn), 0.5f);
+        float2 d = csub(Zk, Zn);
+        float2 Xb = make_float2(0.5f * d.y, -0.5f * d.x);
+        store_pair(dst + (size_t)(2 * m) * ny + 2 * p, Xa, Xb, rows - 2 * p);
+    }
+    __syncthreads();
+    fft_io<L, -1, NP, NT, Rows, false, false, true, MF>(buf, twL, pair_odd, to_lds);
+    __syncthreads();
+    // odd frequencies kx = 2m+1, m < L/2: Z[2m+1] = O[m], Z[2L-2m-1] = O[L-1-m]
+    for (int it = tid; it < (L / 2) * NP; it += NT) {
+        int p = it % NP, m = it / NP;
+        float2 Zk = buf[p * LS + lpad(m)];
+        float2 Zn = cconj(buf[p * LS + lpad(L - 1 - m)]);
+        float2 Xa = cscale(cadd(Zk, Zn), 0.5f);
+        float2 d = csub(Zk, Zn);
+        float2 Xb = make_float2(0.5f * d.y, -0.5f * d.x);
+        store_pair(dst + (size_t)(2 * m + 1) * ny + 2 * p, Xa, Xb, rows - 2 * p);
+    }
+}
+
+// Inverse: the even (odd) inputs Z[2m] (Z[2m+1]) of the packed pair are gathered
+// from S1 (consecutive threads, consecutive y) into LDS; the inverse of the even
+// part is parked in a second LDS region, and the last pass of the odd part
+// combines z[t] = IE[t] + W_2L^-t IO[t] and stores both rows of H directly.
+template <int L, int TY, int MF>
+__global__ __launch_bounds__(NT) void x_inverse_kernel(const XBatch b,
+                                                       const float2* __restrict__ tw_all) {
+    constexpr int NP = TY / 2;
+    constexpr int LS = lpad_c(L) + 1;  // odd stride: the pairs of one frequency hit distinct banks
+    __shared__ float2 buf[NP * LS];
+    __shared__ float2 ie[NP * LS];
+    __shared__ float2 twL[L];
+    __shared__ float2 tw2L[L];  // first half of the length-2L table
+    stage_table(twL, tw_all + L, L);
+    stage_table(tw2L, tw_all + 2 * L, L);
+    const int tid = threadIdx.x;
+    const int gid = xcd_tile(blockIdx.x, gridDim.x);
+    const int item = batch_item(b, gid);
+    const float2* __restrict__ S1 = b.d[item].S1;
+    float* __restrict__ H = b.d[item].H;
+    const int ny = b.d[item].ny, nz = b.d[item].nz;
+    const int nyt = (ny + TY - 1) / TY;
+    const int id = gid - b.start[item];
+    const int y0 = (id % nyt) * TY, z = (id / nyt) % nz, c = id / (nyt * nz);
+    const int rows = min(TY, ny - y0);
+    const float2* src = S1 + (size_t)(c * nz + z) * (L + 1) * ny + y0;
+    float* dst = H + ((size_t)(c * nz + z) * ny + y0) * L;
+    using Rows = RowLines<LS>;
+
+    // Z[k] = Xa[k] + i Xb[k]; for k > L use Hermitian symmetry X[2L-k] = conj(X[k]).
+    // The DC and Nyquist bins of a real row are real: their imaginary parts are dropped.
+    for (int it = tid; it < (L / 2 + 1) * NP; it += NT) {
+        int p = it % NP, m = it / NP, kx = 2 * m;
+        float2 Xa, Xb;
+        load_pair(src + (size_t)kx * ny + 2 * p, Xa, Xb, rows - 2 * p);
+        if (kx == 0 || kx == L) {
+            Xa.y = 0.f;
+            Xb.y = 0.f;
+        }
+        buf[p * LS + lpad(m)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
+        if (kx > 0 && kx < L) buf[p * LS + lpad(L - m)] = make_float2(Xa.x + Xb.y, Xb.x - Xa.y);
+    }
+    __syncthreads();
+    auto from_lds = [&](int p, int t) { return buf[p * LS + lpad(t)]; };
+    auto park = [&](int p, int t, float2 v) { ie[p * LS + lpad(t)] = v; };
+    fft_io<L, +1, NP, NT, Rows, false, false, true, MF>(buf, twL, from_lds, park);
+    __syncthreads();
+    // Odd inputs Z[2m+1]: kx = 2m+1 < L direct, and Z[2L-kx] = conj -> slot L-1-m.
+    for (int it = tid; it < (L / 2) * NP; it += NT) {
+        int p = it % NP, m = it / NP, kx = 2 * m + 1;
+        float2 Xa, Xb;
+        load_pair(src + (size_t)kx * ny + 2 * p, Xa, Xb, rows - 2 * p);
+        buf[p * LS + lpad(m)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
+        buf[p * LS + lpad(L - 1 - m)] = make_float2(Xa.x + Xb.y, Xb.x - Xa.y);
+    }
+    __syncthreads();
+    auto combine = [&](int p, int t, float2 io) {
+        float2 zz = cadd(ie[p * LS + lpad(t)], cmul(cconj(tw2L[t]), io));
+        if (2 * p < rows) dst[(size_t)(2 * p) * L + t] = zz.x;
+        if (2 * p + 1 < rows) dst[(size_t)(2 * p + 1) * L + t] = zz.y;
+    };
+    fft_io<L, +1, NP, NT, Rows, false, false, true, MF>(buf, twL, from_lds, combine);
+}
+
+// nx == 1: no x transform (N_x = 1); S1[c][z][0][y] = M[c][z][y][0]
+__global__ void x_copy_forward_kernel(const float* __restrict__ M, float2* __restrict__ S1,
+                                      size_t n, float scale) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) S1[i] = make_float2(M[i] * scale, 0.f);
+}
+__global__ void x_copy_inverse_kernel(const float2* __restrict__ S1, float* __restrict__ H,
+                                      size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) H[i] = S1[i].x;
+}
+
+
+int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hipStream_t s) {
+    if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "x stage: bad batch size");
+    if (nx == 1) {
+        for (int r = 0; r < b.count; ++r) {
+            size_t n = (size_t)3 * b.d[r].nz * b.d[r].ny;
+            hipLaunchKernelGGL(x_copy_forward_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                               s, b.d[r].M, b.d[r].S1, n, b.d[r].scale);
+        }
+        DM_CHECK_LAUNCH();
+        return DEMAG_OK;
+    }
+    switch (nx) {
+#define BODY(V)                                                                               \
+    {                                                                                         \
+        constexpr int TY = XTile<L, V, false>::TY;                                            \
+        b.start[0] = 0;                                                                       \
+        for (int r = 0; r < b.count; ++r)                                                     \
+            b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;       \
+        DM_MF_DISPATCH(V, hipLaunchKernelGGL((x_forward_kernel<L, TY, MFv>),                  \
+                           dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)          \
+    }
+#define CASE(Lv)                    \
+    case Lv: {                      \
+        constexpr int L = Lv;       \
+        DM_VARIANTS(BODY)           \
+        break;                      \
+    }
+        DM_POW2_CASES(CASE)
+#undef CASE
+#undef BODY
+        default: return fail(DEMAG_EUNSUPPORTED, "x stage: unsupported nx");
+    }
+    DM_CHECK_LAUNCH();
+    return DEMAG_OK;
+}
+
+int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hipStream_t s) {
+    if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "x stage: bad batch size");
+    if (nx == 1) {
+        for (int r = 0; r < b.count; ++r) {
+            size_t n = (size_t)3 * b.d[r].nz * b.d[r].ny;
+            hipLaunchKernelGGL(x_copy_inverse_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                               s, b.d[r].S1, b.d[r].H, n);
+        }
+        DM_CHECK_LAUNCH();
+        return DEMAG_OK;
+    }
+    switch (nx) {
+#define BODY(V)                                                                               \
+    {                                                                                         \
+        constexpr int TY = XTile<L, V, true>::TY;                                             \
+        b.start[0] = 0;                                                                       \
+        for (int r = 0; r < b.count; ++r)                                                     \
+            b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;       \
+        DM_MF_DISPATCH(V, hipLaunchKernelGGL((x_inverse_kernel<L, TY, MFv>),                  \
+                           dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)          \
+    }
+#define CASE(Lv)                    \
+    case Lv: {                      \
+        constexpr int L = Lv;       \
+        DM_VARIANTS(BODY)           \
+        break;                      \
+    }
+        DM_POW2_CASES(CASE)
+#undef CASE
+#undef BODY
+        default: return fail(DEMAG_EUNSUPPORTED, "x stage: unsupported nx");
+    }
+    DM_CHECK_LAUNCH();
+    return DEMAG_OK;
+}
+
+
+}  // namespace dm

@@ -1,0 +1,177 @@
+// stages_z.hip -- z stage: z FFT, the packed symmetric tensor product, z IFFT; and the twiddle table.
+#include "stage_common.h"
+
+namespace dm {
+
+// ============================================================================ z
+// One block: folded ky indices f in [f0, f0 + th) of one kx, each taken together
+// with its mirror ky = Ny - f, so that the kernel values K(kx, |ky|, |kz|) are read
+// once for both.  The mirror slot of f = 0 (which has no mirror) carries the
+// Nyquist column ky = Ny/2 instead.  Column j < TH holds ky = f0 + j, column
+// TH + j holds the mirror of f0 + j.  All stored z planes of the 3 components are
+// loaded into registers together with the K tile (so every global load of the
+// block is in flight at once), then staged in LDS: element (z, c, column) at
+// z * 3NC + c * NC + column, i.e. 3NC interleaved lines of length NZ.
+template <int NZ, int TH, int MF>
+__global__ __launch_bounds__(NT) void z_convolve_kernel(const ZBatch b,
+                                                        const float2* __restrict__ tw_all) {
+    constexpr int NZH = NZ > 1 ? NZ / 2 : 1;   // stored z planes
+    constexpr int KT = NZ > 1 ? NZ / 2 + 1 : 1;  // folded kz values
+    constexpr int NC = 2 * TH;                   // columns per block
+    constexpr int NLN = 3 * NC;
+    __shared__ float2 buf[NZ * NLN];
+    __shared__ float ks[6 * KT * (TH + 1)];      // [comp][kz][f - f0], slot TH = Nyquist
+    __shared__ float2 twZ[NZ];
+    stage_table(twZ, tw_all + NZ, NZ);
+    const int tid = threadIdx.x;
+    const int gid = xcd_tile(blockIdx.x, gridDim.x);
+    const int item = batch_item(b, gid);
+    float2* __restrict__ S2 = b.d[item].S2;
+    const float* __restrict__ K = b.d[item].K;
+    const int X1 = b.d[item].X1, Ny = b.d[item].Ny, Y1 = b.d[item].Y1, Z1 = b.d[item].Z1;
+    const int k0 = b.d[item].k0, xc = b.d[item].xc;
+    const int ny = Ny > 1 ? Ny / 2 : 1;
+    const int th = TH < ny ? TH : ny;
+    const int nft = ny / th;
+    const int id = gid - b.start[item];
+    const int f0 = (id % nft) * th, kl = id / nft, kx = k0 + kl;
+    const size_t P = (size_t)xc * Ny;  // complex elements per z plane of the chunk
+    const size_t cstride = (size_t)NZH * P;
+    float2* col = S2 + (size_t)kl * Ny;
+    const bool nyq = (f0 == 0 && Ny > 1);
+    auto col_ky = [&](int j) -> int {
+        if (j < TH) return j < th ? f0 + j : -1;
+        int jj = j - TH;
+        if (jj >= th) return -1;
+        int f = f0 + jj;
+        if (f == 0) return nyq ? Ny / 2 : -1;
+        return Ny - f;
+    };
+
+    // kernel tile: slot j < TH holds folded ky = f0 + j, slot TH the Nyquist column
+    constexpr int NKL = 6 * KT * (TH + 1);
+    constexpr int PK = (NKL + NT - 1) / NT;
+    float kr[PK];
+#pragma unroll
+    for (int q = 0; q < PK; ++q) {
+        int it = tid + q * NT;
+        kr[q] = 0.f;
+        if (it < NKL) {
+            int j = it % (TH + 1), rest = it / (TH + 1), kz = rest % KT, comp = rest / KT;
+            int f = (j < TH) ? (j < th ? f0 + j : -1) : (nyq ? Ny / 2 : -1);
+            if (f >= 0) kr[q] = K[(((size_t)comp * Z1 + kz) * X1 + kx) * Y1 + f];
+        }
+    }
+    // LDS line (c, column) = c * NC + column; element z of a line at z * NLN + line
+    auto gsrc = [&](int line, int zz) {
+        int c = line / NC, j = line - c * NC;
+        int ky = col_ky(j);
+        return ky >= 0 ? col[c * cstride + zz * P + ky] : make_float2(0.f, 0.f);
+    };
+    auto lds_sink = [&](int line, int k, float2 v) { buf[k * NLN + line] = v; };
+    if constexpr (NZ == 1) {
+        for (int line = tid; line < NLN; line += NT) buf[line] = gsrc(line, 0);
+    } else {
+        fft_io<NZ, -1, NLN, NT, ColLines<NLN>, true, false, true, MF>(buf, twZ, gsrc, lds_sink);
+    }
+    // the kernel tile goes to LDS only now, so its loads overlapped the transform
+#pragma unroll
+    for (int q = 0; q < PK; ++q) {
+        int it = tid + q * NT;
+        if (it < NKL) ks[it] = kr[q];
+    }
+    __syncthreads();
+
+    for (int it = tid; it < NZ * NC; it += NT) {
+        int j = it % NC, kz = it / NC;
+        if (col_ky(j) < 0) continue;
+        int kzf = kz;
+        float sz = 1.f;
+        if (2 * kz > NZ) { kzf = NZ - kz; sz = -1.f; }
+        int jj = j < TH ? j : j - TH;
+        float sy = 1.f;
+        int slot = jj;
+        if (j >= TH) {
+            if (f0 + jj == 0) slot = TH;   // Nyquist column, folded index Ny/2
+            else sy = -1.f;
+        }
+        const float* k0p = ks + kzf * (TH + 1) + slot;
+        constexpr int KC = KT * (TH + 1);
+        float kxx = k0p[0], kyy = k0p[KC], kzz = k0p[2 * KC];
+        float kxy = sy * k0p[3 * KC], kxz = sz * k0p[4 * KC], kyz = sy * sz * k0p[5 * KC];
+        float2* p = buf + kz * NLN + j;
+        float2 mx = p[0], my = p[NC], mz = p[2 * NC];
+        auto dot3 = [](float a, float x, float b, float y, float c, float z) {
+            return fmaf(c, z, fmaf(b, y, a * x));
+        };
+        p[0] = make_float2(dot3(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3(kxx, mx.y, kxy, my.y, kxz, mz.y));
+        p[NC] = make_float2(dot3(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3(kxy, mx.y, kyy, my.y, kyz, mz.y));
+        p[2 * NC] = make_float2(dot3(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3(kxz, mx.y, kyz, my.y, kzz, mz.y));
+    }
+    __syncthreads();
+
+    auto lds_src = [&](int line, int zz) { return buf[zz * NLN + line]; };
+    auto gsink = [&](int line, int zz, float2 v) {
+        int c = line / NC, j = line - c * NC;
+        int ky = col_ky(j);
+        if (ky >= 0) col[c * cstride + zz * P + ky] = v;
+    };
+    if constexpr (NZ == 1) {
+        for (int line = tid; line < NLN; line += NT) gsink(line, 0, buf[line]);
+    } else {
+        fft_io<NZ, +1, NLN, NT, ColLines<NLN>, false, true, true, MF>(buf, twZ, lds_src, gsink);
+    }
+}
+
+
+int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, hipStream_t s) {
+    if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "z stage: bad batch size");
+    switch (Nz) {
+#define BODY(V)                                                                                \
+    {                                                                                          \
+        constexpr int TH = ZTile<NZ, V>::TH;                                                   \
+        b.start[0] = 0;                                                                        \
+        for (int r = 0; r < b.count; ++r) {                                                    \
+            int ny = b.d[r].Ny > 1 ? b.d[r].Ny / 2 : 1;                                        \
+            int th = TH < ny ? TH : ny;                                                        \
+            b.start[r + 1] = b.start[r] + (ny / th) * b.d[r].nk;                               \
+        }                                                                                      \
+        DM_MF_DISPATCH(V, hipLaunchKernelGGL((z_convolve_kernel<NZ, TH, MFv>),                \
+                           dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)          \
+    }
+#define CASE(NZv)                   \
+    case NZv: {                     \
+        constexpr int NZ = NZv;     \
+        DM_VARIANTS(BODY)           \
+        break;                      \
+    }
+        CASE(1) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64) CASE(128) CASE(256)
+#undef CASE
+#undef BODY
+        default: return fail(DEMAG_EUNSUPPORTED, "z stage: unsupported nz");
+    }
+    DM_CHECK_LAUNCH();
+    return DEMAG_OK;
+}
+
+int twiddle_table_length(const Geometry& g) {
+    int m = 2;
+    m = std::max(m, g.Nx);
+    m = std::max(m, g.Ny);
+    m = std::max(m, g.Nz);
+    return m;
+}
+
+void fill_twiddles(float2* host, int Lmax) {
+    // table for length L at offset L (L = 1, 2, 4, ..., Lmax): exp(-2 pi i t/L)
+    host[0] = make_float2(0.f, 0.f);
+    for (int L = 1; L <= Lmax; L *= 2) {
+        for (int t = 0; t < L; ++t) {
+            long double ang = -2.0L * 3.141592653589793238462643383279502884L * t / L;
+            host[L + t] = make_float2((float)cosl(ang), (float)sinl(ang));
+        }
+    }
+}
+
+
+}  // namespace dm

@@ -35,6 +35,11 @@ def test_plan_bytes_and_validation_on_host():
     assert pkg.demag_plan_bytes((32, 32, 256, 4e-9, 4e-9, 4e-9)) == 0
     assert pkg.demag_plan_bytes((32, 32, 4, -4e-9, 4e-9, 4e-9)) == 0
     assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=7) == 0
+    assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=3) == 0
+    # the split-precision MFMA forms need exactly the FP32 plan's memory
+    fp32 = pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9))
+    for f in (pkg.DEMAG_BF16X2_MFMA, pkg.DEMAG_BF16X3_MFMA):
+        assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=f) == fp32
     with pytest.raises(pkg.DemagError) as e:
         pkg.demag_setup((24, 32, 4, 4e-9, 4e-9, 4e-9))
     assert e.value.status == pkg.DEMAG_EUNSUPPORTED
