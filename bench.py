@@ -69,23 +69,29 @@ def geometry(n):
     return N, D
 
 
-def stage_bytes(n):
-    """Algorithmic HBM bytes of one launch of each stage kernel."""
+def stage_bytes(n, form=5):
+    """Algorithmic HBM bytes of one evaluation of each stage (inputs read once,
+    outputs written once, zero padding never stored), for the five-pass form
+    (form 5) or the three-kernel thin-mesh form (form 3: x+z, y conv, z+x)."""
     nx, ny, nz = n
     (Nx, Ny, Nz), (X1, Y1, Z1) = geometry(n)
     cells = nx * ny * nz
     f = 12 * cells                   # one FP32 3-vector field
+    k = 6 * Z1 * X1 * Y1 * 4         # packed real kernel
+    # RK4 stage update, averaged over the four stages: 48, 72, 72, 60 B/cell
+    llg = 63 * cells
+    if form == 3:
+        t = 3 * Nz * X1 * ny * 8     # all Nz transformed planes, ny rows, X1 columns
+        return {"x_fwd": f + t, "z_conv": 2 * t + k, "x_inv": t + f, "llg": llg}
     s1 = 3 * nz * X1 * ny * 8        # complex64 after x
     s2 = 3 * nz * X1 * Ny * 8        # complex64 after y (z padding never stored)
-    k = 6 * Z1 * X1 * Y1 * 4         # packed real kernel
     return {
         "x_fwd": f + s1,
         "y_fwd": s1 + s2 if ny > 1 else 0,
         "z_conv": 2 * (s2 if ny > 1 else s1) + k,
         "y_inv": s2 + s1 if ny > 1 else 0,
         "x_inv": s1 + f,
-        # RK4 stage update, averaged over the four stages: 48, 72, 72, 60 B/cell
-        "llg": 63 * cells,
+        "llg": llg,
     }
 
 
@@ -360,6 +366,7 @@ def main():
     else:
         pkg.demag_autotune(plan, stream)
     variants = [pkg.demag_get_variant(plan, st) for st in range(5)]
+    form = pkg.demag_get_form(plan)
     m0 = torch.from_numpy(W.unit_vectors((n[2], n[1], n[0]), seed=0)).to(dev)
     m = m0.clone()
     params = (cfg["Ms"], cfg["A"], cfg["alpha"], 2.21276e5, (0.0, 0.0, 0.0))
@@ -395,178 +402,14 @@ def main():
 
     ms_per_step = 1e3 * elapsed / args.steps
     value = 4 * cells * args.steps / elapsed / 1e9
-    nbytes = stage_bytes(n)   # per H_d evaluation (per RK stage for "llg")
+    nbytes = stage_bytes(n, form)   # per H_d evaluation (per RK stage for "llg")
     evals = 4 * args.steps
     per_stage = _stage_table(nbytes, stages, evals)
     dom = max(per_stage, key=lambda k: per_stage[k]["avg_us"] * per_stage[k]["launches"])
-    b5 = sum(v for k, v in nbytes.items() if k != "llg")
-    out = {"metric": "demag H_d evals: Gcells/s + % HBM roofline", "value": round(cells / t_field / 1e9, 3),
-           "unit": "Gcells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(1e3 * t_field, 4), "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": cfg["name"], "mesh": list(n), "yz_chunks": nch},
-           "roofline": {"bound": "hbm", "kernel": dom, "achieved": per_stage[dom]["GB_per_s"],
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(per_stage[dom]["GB_per_s"] / HBM_PEAK_GBS, 4), "traffic": None},
-           "stages": per_stage, "demag_field_effective_frac": round(b5 / t_field / 1e9 / HBM_PEAK_GBS, 4),
-           "timed_with_events_ms": round(1e3 * el / args.steps, 4)}
-    return out
-
-
-def atomistic_bench(pkg, args):
-    """Heun steps of 1024x1024x256 spins (a = 0.4 nm, J = 1e-21 J, mu_s = 1 muB,
-    alpha = 0.05, dt = 1e-15 s, T = 0), demag on 4^3-spin macrocells."""
-    import torch
-    import workloads as W
-    cfg = W.ATOMISTIC
-    n = cfg["n"]
-    spins = n[0] * n[1] * n[2]
-    stream = torch.cuda.current_stream()
-    plan = pkg.atom_setup((n[0], n[1], n[2], cfg["a"], cfg["macro"]), stream=stream)
-    S = torch.from_numpy(W.unit_vectors((n[2], n[1], n[0]), seed=0)).cuda()
-    prm = (cfg["J"], cfg["mu_s"], cfg["alpha"], 2.21276e5, (0.0, 0.0, 0.0))
-    pkg.atom_step(plan, S, prm, cfg["dt"], args.warmup, stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pkg.atom_step(plan, S, prm, cfg["dt"], args.steps, stream)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    pkg.atom_destroy(plan)
-    norm_err = float((S.norm(dim=0) - 1).abs().max())
-    # Heun step bytes: 2 macro averages (12 B/spin each), predictor (read 12, write 24),
-    # corrector (read 36, write 12); neighbour re-reads come from cache
-    per_spin = 2 * 12 + 36 + 48
-    ms = 1e3 * el / args.steps
-    return {"metric": "atomistic spin-steps/s", "value": round(spins * args.steps / el / 1e9, 3),
-            "unit": "Gspin-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-            "config": {"workload": cfg["name"], "lattice": list(n), "macro": cfg["macro"]},
-            "roofline": {"bound": "hbm", "kernel": "whole Heun step", "achieved":
-                         round(per_spin * spins / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": round(per_spin * spins / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                         "traffic": None},
-            "max_norm_error": norm_err}
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-serve", action="store_true", help="skip the short serving sample")
-    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
-                    help="first run one plain device copy of MB megabytes (a known-size "
-                         "reference for hardware byte counters)")
-    ap.add_argument("--workload", default="thin_film", choices=("thin_film", "large_film", "atomistic"),
-                    help="thin_film (default): 512x512x16 RK4 LLG; large_film: 1024x1024x32 "
-                         "demag_field; atomistic: 1024x1024x256 spins, Heun, 4^3 macrocells")
-    ap.add_argument("--variants", type=lambda s: [int(v) for v in s.split(",")], default=None,
-                    help="pin the tile variant of the five FFT stages (e.g. 1,1,1,1,1) instead "
-                         "of autotuning")
-    ap.add_argument("--chunks", type=int, default=0,
-                    help="pin the number of chunks the y/z stages run in instead of autotuning")
-    ap.add_argument("--serve-full", action="store_true",
-                    help="only the full serving workload: 256 requests x 1000 RK4 steps, "
-                         "Poisson loads 0.5/0.8/0.95 of the closed-loop throughput")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(use --gpus 1)", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import paper_2308_08447_amd as pkg
-    import workloads as W
-
-    if args.copy_probe:
-        src = torch.empty(args.copy_probe * 2**20 // 4, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    if args.serve_full:
-        res = serve_bench(pkg, 256, 1000, (0.5, 0.8, 0.95))
-        print(json.dumps({"metric": "serve p50/p99 latency", "data": "synthetic",
-                          "config": {"workload": "serving: 256 LLG relaxations, meshes "
-                                     "{32..512}^2 x {1,2,4,8}, 1000 RK4 steps each"},
-                          "serve": res}), flush=True)
-        return
-
-    if args.workload == "large_film":
-        print(json.dumps(large_film_bench(pkg, args)), flush=True)
-        return
-    if args.workload == "atomistic":
-        print(json.dumps(atomistic_bench(pkg, args)), flush=True)
-        return
-
-    cfg = W.THIN_FILM
-    n, cell = cfg["n"], cfg["cell"]
-    cells = n[0] * n[1] * n[2]
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
-    plan = pkg.demag_setup(n + cell, stream=stream)
-    if args.variants or args.chunks:
-        for st, v in enumerate(args.variants or []):
-            pkg.demag_set_variant(plan, st, v)
-        if args.chunks:
-            pkg.demag_set_chunks(plan, args.chunks)
-    else:
-        pkg.demag_autotune(plan, stream)
-    variants = [pkg.demag_get_variant(plan, st) for st in range(5)]
-    m0 = torch.from_numpy(W.unit_vectors((n[2], n[1], n[0]), seed=0)).to(dev)
-    m = m0.clone()
-    params = (cfg["Ms"], cfg["A"], cfg["alpha"], 2.21276e5, (0.0, 0.0, 0.0))
-
-    for _ in range(args.warmup):
-        pkg.llg_step(plan, m, params, cfg["dt"], 1, stream)
-    torch.cuda.synchronize()
-    nch = pkg.demag_get_chunks(plan)
-    pkg.demag_timing_enable(plan, 4 * args.steps * nch)
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        pkg.llg_step(plan, m, params, cfg["dt"], 1, stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stages = pkg.demag_timing_read(plan)
-    pkg.demag_timing_enable(plan, 0)
-
-    # standalone demag_field throughput (not the headline; same stream, no events)
-    M = (m0 * cfg["Ms"]).contiguous()
-    H = torch.empty_like(M)
-    for _ in range(3):
-        pkg.demag_field(plan, M, H, stream)
-    torch.cuda.synchronize()
-    reps = 4 * args.steps
-    t1 = time.perf_counter()
-    for _ in range(reps):
-        pkg.demag_field(plan, M, H, stream)
-    torch.cuda.synchronize()
-    t_field = (time.perf_counter() - t1) / reps
-    pkg.demag_destroy(plan)
-
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = 4 * cells * args.steps / elapsed / 1e9
-    nbytes = stage_bytes(n)   # per H_d evaluation (per RK stage for "llg")
-    evals = 4 * args.steps
-    per_stage = {}
-    for name, (tot_ms, cnt) in stages.items():
-        if cnt:
-            # the y/z stages run once per chunk: bytes per launch = bytes per evaluation / chunks
-            per_launch = nbytes[name] * evals / cnt
-            avg = tot_ms / cnt
-            per_stage[name] = {"avg_us": round(1e3 * avg, 2), "launches": cnt,
-                               "bytes_per_launch": int(per_launch),
-                               "GB_per_s": round(per_launch / (avg * 1e-3) / 1e9, 1),
-                               "us_per_eval": round(1e3 * tot_ms / evals, 2)}
-    dom = max(per_stage, key=lambda k: per_stage[k]["avg_us"] * per_stage[k]["launches"])
     achieved = per_stage[dom]["GB_per_s"]
-    b5 = sum(v for k, v in nbytes.items() if k != "llg")
+    # the reference byte count is the five-pass one (B5), whichever form runs
+    b5 = sum(v for k, v in stage_bytes(n, 5).items() if k != "llg")
+    b_form = sum(v for k, v in nbytes.items() if k != "llg")
 
     out = {
         "metric": "demag H_d evals: Gcells/s + % HBM roofline; serve p50/p99 latency",
@@ -583,6 +426,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"], "mesh": list(n), "cell_m": list(cell),
                    "hd_evals_per_step": 4, "global_batch": 1, "parallelism": "none",
+                   "form": "thin (x+z, y conv, z+x)" if form == 3 else "five-pass",
                    "stage_variants": variants, "yz_chunks": nch},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -592,6 +436,8 @@ def main():
         "demag_field_gcells_per_s": round(cells / t_field / 1e9, 3),
         "demag_field_us": round(1e6 * t_field, 1),
         "demag_field_effective_frac": round(b5 / t_field / 1e9 / HBM_PEAK_GBS, 4),
+        "demag_field_bytes_b5": b5,
+        "demag_field_bytes_this_form": b_form,
         "llg_cell_steps_per_s": round(cells * args.steps / elapsed, 1),
     }
     if not args.no_serve:

@@ -214,6 +214,22 @@ int demag_get_chunks(demag_plan* plan, int32_t* nchunks);
 int demag_set_variant(demag_plan* plan, int32_t stage, int32_t variant);
 int demag_get_variant(demag_plan* plan, int32_t stage, int32_t* variant);
 
+/*
+ * demag_get_form -- which kernel sequence the plan runs (fixed at set-up):
+ *   DEMAG_FORM_FIVE_PASS   x R2C, y FFT, z convolution, y IFFT, x C2R
+ *                          (stages X_FWD, Y_FWD, Z_CONV, Y_INV, X_INV);
+ *   DEMAG_FORM_THIN        FP32 plans of thin meshes (32 <= n_x <= 1024,
+ *                          16 <= n_y <= 512, n_z <= 16): x R2C with the z FFT
+ *                          (timed as X_FWD), y FFT + tensor product + y IFFT
+ *                          (timed as Z_CONV), z IFFT with the x C2R (X_INV).
+ *                          The tile variants and the chunk count have no effect.
+ * Both compute the same H (Eq. 1) to FP32 rounding.
+ *   plan  in   plan;   form  out  one of the values below.
+ * Errors: EINVAL (NULL argument).
+ */
+enum { DEMAG_FORM_FIVE_PASS = 5, DEMAG_FORM_THIN = 3 };
+int demag_get_form(demag_plan* plan, int32_t* form);
+
 /* ---- serving: continuous batching of independent LLG simulations --------- */
 /*
  * A server owns a worker thread and a HIP stream.  Requests (a mesh, LLG

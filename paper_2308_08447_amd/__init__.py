@@ -32,7 +32,7 @@ EXPORTS = (
     "demag_setup", "demag_field", "demag_plan_bytes", "demag_get_kernel", "demag_destroy",
     "llg_step", "atom_setup", "atom_step", "atom_destroy", "demag_timing_enable",
     "demag_timing_read", "demag_autotune", "demag_set_variant", "demag_get_variant",
-    "demag_set_chunks", "demag_get_chunks", "serve_open", "serve_submit", "serve_wait",
+    "demag_set_chunks", "demag_get_chunks", "demag_get_form", "serve_open", "serve_submit", "serve_wait",
     "serve_get_stats", "serve_close", "demag_last_error",
 )
 SERVE_GRAPHS = 1
@@ -112,6 +112,7 @@ def load(path=None):
         "demag_get_variant": ([vp, ctypes.c_int32, P(ctypes.c_int32)], ctypes.c_int),
         "demag_set_chunks": ([vp, ctypes.c_int32], ctypes.c_int),
         "demag_get_chunks": ([vp, P(ctypes.c_int32)], ctypes.c_int),
+        "demag_get_form": ([vp, P(ctypes.c_int32)], ctypes.c_int),
         "serve_open": ([sz, ctypes.c_int32, ctypes.c_uint32, P(vp)], ctypes.c_int),
         "serve_submit": ([vp, P(demag_mesh), P(llg_params), ctypes.c_double, ctypes.c_int32, vp,
                           P(ctypes.c_uint64)], ctypes.c_int),
@@ -226,6 +227,17 @@ def demag_set_chunks(plan, nchunks):
 def demag_get_chunks(plan):
     v = ctypes.c_int32()
     _check(load().demag_get_chunks(plan, ctypes.byref(v)))
+    return v.value
+
+
+DEMAG_FORM_FIVE_PASS = 5
+DEMAG_FORM_THIN = 3
+
+
+def demag_get_form(plan):
+    """DEMAG_FORM_FIVE_PASS or DEMAG_FORM_THIN (the three-kernel thin-mesh form)."""
+    v = ctypes.c_int32()
+    _check(load().demag_get_form(plan, ctypes.byref(v)))
     return v.value
 
 

@@ -13,7 +13,8 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdemag.so")
-SOURCES = ["capi.hip", "stages_x.hip", "stages_y.hip", "stages_z.hip", "tensor.hip", "dynamics.hip",
+SOURCES = ["capi.hip", "stages_x.hip", "stages_y.hip", "stages_z.hip", "stages_xz.hip", "tensor.hip",
+           "dynamics.hip",
            "serve.hip"]
 ARCH = os.environ.get("DEMAG_OFFLOAD_ARCH", "gfx950")
 

@@ -147,7 +147,12 @@ int s2_planes(const Geometry& g) {
     return planes >= (size_t)g.X1 ? g.X1 : (int)planes;
 }
 
-size_t workspace_bytes(const Geometry& g) {
+bool uses_xz(const Geometry& g, uint32_t flags) {
+    return flags == DEMAG_FP32 && xz_supported(g.nx, g.ny, g.nz);
+}
+
+size_t workspace_bytes(const Geometry& g, uint32_t flags) {
+    if (uses_xz(g, flags)) return xz_t_elems(g.nx, g.ny, g.nz) * sizeof(float2);
     size_t b = g.s1_elems() * sizeof(float2);
     if (g.ny > 1) b += (size_t)3 * g.nz * s2_planes(g) * g.Ny * sizeof(float2);
     return b;
@@ -178,6 +183,7 @@ void free_plan(demag_plan* p) {
     free_timing(p);
     (void)hipFree(p->S1);
     if (p->S2 != p->S1) (void)hipFree(p->S2);
+    (void)hipFree(p->T);
     (void)hipFree(p->rk);
     delete p;
 }
@@ -201,20 +207,28 @@ int create_plan(const demag_mesh* mesh, uint32_t flags, hipStream_t s, demag_pla
         return code;
     };
     if ((rc = device_twiddles(&p->tw))) return bail(rc);
-    if ((rc = dev_alloc((void**)&p->S1, g.s1_elems() * sizeof(float2), "S1"))) return bail(rc);
-    p->xc = s2_planes(g);
-    p->nch = (g.X1 + p->xc - 1) / p->xc;
-    if (g.ny > 1) {
-        if ((rc = dev_alloc((void**)&p->S2, (size_t)3 * g.nz * p->xc * g.Ny * sizeof(float2), "S2")))
+    p->xz = uses_xz(g, flags);
+    if (p->xz) {
+        if ((rc = dev_alloc((void**)&p->T, xz_t_elems(g.nx, g.ny, g.nz) * sizeof(float2), "T")))
             return bail(rc);
+        p->xc = g.X1;
+        p->nch = 1;
     } else {
-        p->S2 = p->S1;
+        if ((rc = dev_alloc((void**)&p->S1, g.s1_elems() * sizeof(float2), "S1"))) return bail(rc);
+        p->xc = s2_planes(g);
+        p->nch = (g.X1 + p->xc - 1) / p->xc;
+        if (g.ny > 1) {
+            if ((rc = dev_alloc((void**)&p->S2, (size_t)3 * g.nz * p->xc * g.Ny * sizeof(float2), "S2")))
+                return bail(rc);
+        } else {
+            p->S2 = p->S1;
+        }
     }
     if ((rc = get_spectrum(g, mesh->dx, mesh->dy, mesh->dz, s, &p->spec))) return bail(rc);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find({g.nx, g.ny, g.nz, p->mf});
-        if (it != g_tuned.end()) {
+        if (it != g_tuned.end() && !p->xz) {
             for (int i = 0; i < 5; ++i) p->variant[i] = it->second.variant[i];
             p->nch = it->second.nch;
         }
@@ -254,6 +268,13 @@ static YDesc ydesc(demag_plan* p, int k0, int nk) {
 static ZDesc zdesc(demag_plan* p, int k0, int nk) {
     return ZDesc{p->S2, p->spec->K, p->g.X1, p->g.Ny, p->g.Y1, p->g.Z1, k0, nk, p->xc};
 }
+static XZDesc xzdesc(demag_plan* p, const float* M, float* H, float scale) {
+    return XZDesc{M, H, p->T, p->g.ny, scale};
+}
+static YCDesc ycdesc(demag_plan* p) {
+    const Geometry& g = p->g;
+    return YCDesc{p->T, p->spec->K, g.X1, g.Y1, g.Z1, (g.X1 + 3) / 4};
+}
 template <class D>
 static StageBatch<D> one(const D& d) {
     StageBatch<D> b;
@@ -267,6 +288,18 @@ static StageBatch<D> one(const D& d) {
 static int run_field_single(demag_plan* p, const float* M, float* H, float scale, hipStream_t s) {
     const Geometry& g = p->g;
     int rc;
+    if (p->xz) {  // x + z forward, y convolution, z + x inverse
+        {
+            StageTimer t(p, DEMAG_STAGE_X_FWD, s);
+            if ((rc = launch_xz_forward(one(xzdesc(p, M, H, scale)), g.nx, g.nz, p->tw, s))) return rc;
+        }
+        {
+            StageTimer t(p, DEMAG_STAGE_Z_CONV, s);
+            if ((rc = launch_yconv(one(ycdesc(p)), g.ny, g.Nz, p->tw, s))) return rc;
+        }
+        StageTimer t(p, DEMAG_STAGE_X_INV, s);
+        return launch_xz_inverse(one(xzdesc(p, M, H, scale)), g.nx, g.nz, p->tw, s);
+    }
     {
         StageTimer t(p, DEMAG_STAGE_X_FWD, s);
         if ((rc = launch_x_forward(one(xdesc(p, M, H, scale)), g.nx, p->variant[0], p->mf, p->tw, s))) return rc;
@@ -318,13 +351,38 @@ int run_fields(demag_plan* const* plans, const float* const* M, float* const* H,
                const float* scale, int n, hipStream_t s) {
     if (n == 1) return run_field_single(plans[0], M[0], H[0], scale[0], s);
     int rc;
-    std::vector<int> items;
+    std::vector<int> items, xitems;
     for (int i = 0; i < n; ++i) {
         const demag_plan* p = plans[i];
-        if (p->g.ny > 1 && p->nch > 1) {  // several chunks: not batched
+        if (p->xz) {
+            xitems.push_back(i);
+        } else if (p->g.ny > 1 && p->nch > 1) {  // several chunks: not batched
             if ((rc = run_field_single(plans[i], M[i], H[i], scale[i], s))) return rc;
         } else {
             items.push_back(i);
+        }
+    }
+    if (!xitems.empty()) {
+        const float2* tw = plans[xitems[0]]->tw;
+        auto by_xz = groups(xitems, [&](int i) { return plans[i]->g.nx * 64LL + plans[i]->g.nz; });
+        auto by_yc = groups(xitems, [&](int i) { return plans[i]->g.ny * 64LL + plans[i]->g.Nz; });
+        for (auto& grp : by_xz) {
+            XZBatch b;
+            b.count = (int)grp.size();
+            for (int r = 0; r < b.count; ++r) b.d[r] = xzdesc(plans[grp[r]], M[grp[r]], H[grp[r]], scale[grp[r]]);
+            if ((rc = launch_xz_forward(b, plans[grp[0]]->g.nx, plans[grp[0]]->g.nz, tw, s))) return rc;
+        }
+        for (auto& grp : by_yc) {
+            YCBatch b;
+            b.count = (int)grp.size();
+            for (int r = 0; r < b.count; ++r) b.d[r] = ycdesc(plans[grp[r]]);
+            if ((rc = launch_yconv(b, plans[grp[0]]->g.ny, plans[grp[0]]->g.Nz, tw, s))) return rc;
+        }
+        for (auto& grp : by_xz) {
+            XZBatch b;
+            b.count = (int)grp.size();
+            for (int r = 0; r < b.count; ++r) b.d[r] = xzdesc(plans[grp[r]], M[grp[r]], H[grp[r]], scale[grp[r]]);
+            if ((rc = launch_xz_inverse(b, plans[grp[0]]->g.nx, plans[grp[0]]->g.nz, tw, s))) return rc;
         }
     }
     if (items.empty()) return DEMAG_OK;
@@ -467,7 +525,7 @@ size_t demag_plan_bytes(const demag_mesh* mesh, uint32_t flags) {
     Geometry g;
     if (!valid_flags(flags)) return 0;
     if (check_mesh(mesh, &g) != DEMAG_OK) return 0;
-    return g.k_elems() * sizeof(float) + workspace_bytes(g);
+    return g.k_elems() * sizeof(float) + workspace_bytes(g, flags);
 }
 
 int demag_setup(const demag_mesh* mesh, uint32_t flags, void* stream, demag_plan** out) {
@@ -544,6 +602,12 @@ int demag_set_chunks(demag_plan* plan, int32_t nchunks) {
     return DEMAG_OK;
 }
 
+int demag_get_form(demag_plan* plan, int32_t* form) {
+    if (!plan || !form) return fail(DEMAG_EINVAL, "NULL argument");
+    *form = plan->xz ? DEMAG_FORM_THIN : DEMAG_FORM_FIVE_PASS;
+    return DEMAG_OK;
+}
+
 int demag_get_chunks(demag_plan* plan, int32_t* nchunks) {
     if (!plan || !nchunks) return fail(DEMAG_EINVAL, "NULL argument");
     *nchunks = plan->nch;
@@ -589,7 +653,7 @@ int demag_autotune(demag_plan* plan, void* stream) {
     //    in one tile shape only)
     rc = run_field_single(plan, M, H, 1.0f, s);
     const int per = (g.X1 + plan->nch - 1) / plan->nch;
-    for (int st = 0; st < 5 && !rc && plan->mf == 0; ++st) {
+    for (int st = 0; st < 5 && !rc && plan->mf == 0 && !plan->xz; ++st) {
         if ((st == 1 || st == 3) && g.ny == 1) continue;
         double best = 1e30;
         int best_v = plan->variant[st];
@@ -614,7 +678,7 @@ int demag_autotune(demag_plan* plan, void* stream) {
         plan->variant[st] = best_v;
     }
     // 2. number of chunks, timing the whole evaluation
-    if (!rc && g.ny > 1) {
+    if (!rc && g.ny > 1 && !plan->xz) {
         const int nmin = (g.X1 + plan->xc - 1) / plan->xc;
         double best = 1e30;
         int best_n = plan->nch;

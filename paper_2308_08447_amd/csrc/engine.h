@@ -68,6 +68,21 @@ struct StageBatch {
     int start[MAXB + 1];  // block prefix sums (filled by the launcher)
     int count;
 };
+// three-kernel form for thin meshes (stages_xz.hip); nx, nz and ny are launch constants
+struct XZDesc {
+    const float* M;       // xz forward input
+    float* H;             // xz inverse output
+    float2* T;            // [3][Nz][G][ny][4] spectra
+    int ny;
+    float scale;          // applied to M
+};
+struct YCDesc {
+    float2* T;
+    const float* K;       // [6][Z1][X1][Y1]
+    int X1, Y1, Z1, G;
+};
+using XZBatch = StageBatch<XZDesc>;
+using YCBatch = StageBatch<YCDesc>;
 using XBatch = StageBatch<XDesc>;
 using YBatch = StageBatch<YDesc>;
 using ZBatch = StageBatch<ZDesc>;
@@ -77,6 +92,11 @@ int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hi
 int launch_y_forward(YBatch b, int ny, int variant, int mf, const float2* tw, hipStream_t s);
 int launch_y_inverse(YBatch b, int ny, int variant, int mf, const float2* tw, hipStream_t s);
 int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, hipStream_t s);
+bool xz_supported(int nx, int ny, int nz);
+size_t xz_t_elems(int nx, int ny, int nz);
+int launch_xz_forward(XZBatch b, int nx, int nz, const float2* tw, hipStream_t s);
+int launch_yconv(YCBatch b, int ny, int Nz, const float2* tw, hipStream_t s);
+int launch_xz_inverse(XZBatch b, int nx, int nz, const float2* tw, hipStream_t s);
 // Largest transform length the twiddle table must hold for this geometry.
 int twiddle_table_length(const Geometry& g);
 // Fills the host table (2 * Lmax float2) with exp(-2 pi i t/L) at offset L.

@@ -29,7 +29,9 @@ int get_spectrum(const Geometry& g, double dx, double dy, double dz, hipStream_t
 int device_twiddles(const float2** out);
 
 // Bytes of the FFT workspace (S1 + S2 chunk buffer) and of the RK4 buffers.
-size_t workspace_bytes(const Geometry& g);
+// The three-kernel thin-mesh form is used by FP32 plans of supported sizes.
+bool uses_xz(const Geometry& g, uint32_t flags);
+size_t workspace_bytes(const Geometry& g, uint32_t flags);
 size_t rk_bytes(const Geometry& g);
 int s2_planes(const Geometry& g);
 
@@ -48,6 +50,8 @@ struct demag_plan {
     const float2* tw = nullptr;
     float2* S1 = nullptr;
     float2* S2 = nullptr;   // chunk buffer of xc kx planes; == S1 (xc = X1) when ny == 1
+    bool xz = false;        // three-kernel form (T instead of S1 / S2)
+    float2* T = nullptr;    // [3][Nz][G][ny][4] spectra of the three-kernel form
     int xc = 1;             // kx planes S2 holds
     int nch = 1;            // chunks the y/z stages are split into (>= ceil(X1 / xc))
     float* rk = nullptr;    // RK4 buffers (lazily allocated): H, A, B, acc, each 3 N floats

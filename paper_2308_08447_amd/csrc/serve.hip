@@ -306,7 +306,7 @@ int serve_submit(demag_server* s, const demag_mesh* mesh, const llg_params* para
     r->nsteps = nsteps;
     r->g = g;
     r->host.assign(m0_host, m0_host + 3 * g.cells());
-    r->bytes = dm::workspace_bytes(g) + dm::rk_bytes(g) + 3 * g.cells() * sizeof(float);
+    r->bytes = dm::workspace_bytes(g, DEMAG_FP32) + dm::rk_bytes(g) + 3 * g.cells() * sizeof(float);
     r->t_submit = Clock::now();
     {
         std::lock_guard<std::mutex> lk(s->mu);

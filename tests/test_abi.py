@@ -36,10 +36,10 @@ def test_plan_bytes_and_validation_on_host():
     assert pkg.demag_plan_bytes((32, 32, 4, -4e-9, 4e-9, 4e-9)) == 0
     assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=7) == 0
     assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=3) == 0
-    # the split-precision MFMA forms need exactly the FP32 plan's memory
-    fp32 = pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9))
-    for f in (pkg.DEMAG_BF16X2_MFMA, pkg.DEMAG_BF16X3_MFMA):
-        assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=f) == fp32
+    # the two split-precision MFMA forms need the same memory
+    x2 = pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=pkg.DEMAG_BF16X2_MFMA)
+    assert x2 > 0
+    assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=pkg.DEMAG_BF16X3_MFMA) == x2
     with pytest.raises(pkg.DemagError) as e:
         pkg.demag_setup((24, 32, 4, 4e-9, 4e-9, 4e-9))
     assert e.value.status == pkg.DEMAG_EUNSUPPORTED
@@ -60,13 +60,23 @@ def test_plan_bytes_and_validation_on_host():
 
 
 def test_plan_bytes_formula():
-    nx, ny, nz = 512, 512, 16
+    # five-pass form (n_z > 16): packed kernel + S1 + the y/z chunk buffer
+    nx, ny, nz = 512, 512, 32
     X1, Y1, Z1 = nx + 1, ny + 1, nz + 1
     plane = 3 * nz * 2 * ny * 8                  # one kx plane of the y/z spectra
     planes = min(X1, (128 << 20) // plane)       # the chunk buffer is capped at 128 MB
     expect = 6 * Z1 * X1 * Y1 * 4 + 3 * nz * X1 * ny * 8 + planes * plane
     assert pkg.demag_plan_bytes((nx, ny, nz, 4e-9, 4e-9, 4e-9)) == expect
-    # small meshes hold every plane
-    n = (32, 32, 4)
-    small = 6 * 5 * 33 * 33 * 4 + 3 * 4 * 33 * 32 * 8 + 3 * 4 * 33 * 64 * 8
-    assert pkg.demag_plan_bytes(n + (4e-9, 4e-9, 4e-9)) == small
+    # the MFMA forms always take the five-pass form
+    nx, ny, nz = 512, 512, 16
+    X1, Y1, Z1 = nx + 1, ny + 1, nz + 1
+    plane = 3 * nz * 2 * ny * 8
+    planes = min(X1, (128 << 20) // plane)
+    expect = 6 * Z1 * X1 * Y1 * 4 + 3 * nz * X1 * ny * 8 + planes * plane
+    assert pkg.demag_plan_bytes((nx, ny, nz, 4e-9, 4e-9, 4e-9), flags=pkg.DEMAG_BF16X3_MFMA) == expect
+    # three-kernel thin-mesh form: packed kernel + T[3][2nz][ceil((nx+1)/4)][ny][4]
+    for nx, ny, nz in [(512, 512, 16), (32, 32, 4), (64, 16, 1), (1024, 512, 2)]:
+        X1, Y1, Z1 = nx + 1, ny + 1, (nz + 1 if nz > 1 else 1)
+        NZ = 2 * nz if nz > 1 else 1
+        expect = 6 * Z1 * X1 * Y1 * 4 + 3 * NZ * ((X1 + 3) // 4) * ny * 4 * 8
+        assert pkg.demag_plan_bytes((nx, ny, nz, 4e-9, 4e-9, 4e-9)) == expect, (nx, ny, nz)

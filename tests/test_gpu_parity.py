@@ -47,6 +47,9 @@ SHAPES = [
     (32, 32, 4), (1, 1, 1), (2, 1, 1), (1, 8, 1), (8, 1, 1), (16, 1, 4), (4, 4, 2),
     (8, 8, 8), (64, 32, 8), (128, 64, 2), (32, 64, 1), (8, 4, 64), (4, 4, 128),
     (256, 16, 2), (16, 256, 1), (2048, 4, 1), (4, 2048, 2),
+    # three-kernel thin-mesh form (32 <= nx <= 1024, 16 <= ny <= 512, nz <= 16)
+    (1024, 64, 4), (512, 32, 16), (128, 512, 16), (64, 16, 16), (32, 16, 1), (1024, 16, 16),
+    (256, 128, 8), (32, 512, 2),
 ]
 
 
@@ -63,9 +66,10 @@ def test_field_matches_oracle(gpu_lib, torch_dev, n):
     assert max(errs) <= TOL, errs
 
 
-def test_field_matches_direct_sum_small(gpu_lib, torch_dev):
+@pytest.mark.parametrize("n", [(8, 8, 4), (32, 16, 4)], ids=["8x8x4", "32x16x4"])
+def test_field_matches_direct_sum_small(gpu_lib, torch_dev, n):
     import paper_2308_08447_amd as pkg
-    n, cell = (8, 8, 4), (4e-9, 3e-9, 2e-9)
+    cell = (4e-9, 3e-9, 2e-9)
     _say("demag_field vs direct sum", n, cell)
     M = W.magnetisation(n, seed=3)
     H = _gpu_field(pkg, torch_dev, n, cell, M)
