@@ -273,7 +273,7 @@ static XZDesc xzdesc(demag_plan* p, const float* M, float* H, float scale) {
 }
 static YCDesc ycdesc(demag_plan* p) {
     const Geometry& g = p->g;
-    return YCDesc{p->T, p->spec->K, g.X1, g.Y1, g.Z1, (g.X1 + 3) / 4};
+    return YCDesc{p->T, p->spec->K, g.X1, g.Y1, g.Z1, xz_groups(g.X1)};
 }
 template <class D>
 static StageBatch<D> one(const D& d) {

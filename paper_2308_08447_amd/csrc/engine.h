@@ -94,6 +94,7 @@ int launch_y_inverse(YBatch b, int ny, int variant, int mf, const float2* tw, hi
 int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, hipStream_t s);
 bool xz_supported(int nx, int ny, int nz);
 size_t xz_t_elems(int nx, int ny, int nz);
+int xz_groups(int X1);  // kx groups of T
 int launch_xz_forward(XZBatch b, int nx, int nz, const float2* tw, hipStream_t s);
 int launch_yconv(YCBatch b, int ny, int Nz, const float2* tw, hipStream_t s);
 int launch_xz_inverse(XZBatch b, int nx, int nz, const float2* tw, hipStream_t s);

@@ -84,6 +84,37 @@ __device__ __forceinline__ void dft(float2* v) {
     }
 }
 
+// v * exp(DIR 2 pi i k / 16), k < 8
+template <int DIR>
+__device__ __forceinline__ float2 rot16(int k, float2 v) {
+    if (k == 0) return v;
+    if (k == 4) return mul_i<DIR>(v);
+    return cmul(w16<DIR>(k), v);
+}
+
+// DFT of size R whose inputs R/2 .. R-1 are zero: the even outputs are the
+// R/2-point DFT of x, the odd outputs the R/2-point DFT of x[r] W_R^r.
+template <int R, int DIR>
+__device__ __forceinline__ void dft_half_in(float2* v) {
+    if constexpr (R <= 2) {
+        v[1] = v[0];
+    } else {
+        float2 e[R / 2], o[R / 2];
+#pragma unroll
+        for (int r = 0; r < R / 2; ++r) {
+            e[r] = v[r];
+            o[r] = rot16<DIR>(r * (16 / R), v[r]);
+        }
+        dft<R / 2, DIR>(e);
+        dft<R / 2, DIR>(o);
+#pragma unroll
+        for (int m = 0; m < R / 2; ++m) {
+            v[2 * m] = e[m];
+            v[2 * m + 1] = o[m];
+        }
+    }
+}
+
 constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 
 // Radix of pass p for a length-L transform: ceil(log2 L / 4) passes, bits spread evenly.
@@ -117,9 +148,15 @@ constexpr int lpad_c(int i) { return i + (i >> 4); }
 
 // Addressing policy for lines laid out contiguously: line l, element i at
 // base + l * LS + lpad(i); butterflies are enumerated j-fastest within a line.
+// Both policies also give off(n): the LDS distance between elements i and i + n
+// of a line for the index patterns of a power-of-two Stockham pass (n a multiple
+// of the butterfly stride, i the butterfly's base), which is a compile-time
+// constant: with one padding element per 16, i + n never carries past a
+// 16-element boundary that n itself does not cross.
 template <int LS>
 struct RowLines {
     static __device__ __forceinline__ int idx(int line, int i) { return line * LS + lpad(i); }
+    static constexpr int off(int n) { return lpad_c(n); }
     template <int NB>
     static __device__ __forceinline__ void split(int b, int& line, int& j) { line = b / NB; j = b - line * NB; }
 };
@@ -129,6 +166,7 @@ struct RowLines {
 template <int NL>
 struct ColLines {
     static __device__ __forceinline__ int idx(int line, int i) { return i * NL + line; }
+    static constexpr int off(int n) { return n * NL; }
     template <int NB>
     static __device__ __forceinline__ void split(int b, int& line, int& j) { j = b / NL; line = b - j * NL; }
 };
@@ -147,8 +185,9 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
         if (TOT % NT == 0 || b < TOT) {
             int line, j;
             Addr::template split<NB>(b, line, j);
+            const float2* src = buf + Addr::idx(line, j);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = buf[Addr::idx(line, j + r * NB)];
+            for (int r = 0; r < R; ++r) v[q][r] = src[Addr::off(r * NB)];
             if constexpr (NS > 1) {
                 int k = j % NS;
 #pragma unroll
@@ -169,9 +208,9 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
             int line, j;
             Addr::template split<NB>(b, line, j);
             int k = j % NS;
-            int base = (j / NS) * NS * R + k;
+            float2* dst = buf + Addr::idx(line, (j / NS) * NS * R + k);
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[Addr::idx(line, base + r * NS)] = v[q][r];
+            for (int r = 0; r < R; ++r) dst[Addr::off(r * NS)] = v[q][r];
         }
     }
     __syncthreads();
@@ -224,10 +263,12 @@ __device__ __forceinline__ void first_pass(float2* buf, Src& src) {
         if (TOT % NT == 0 || b < TOT) {
             int line, j;
             Addr::template split<NB>(b, line, j);
-            dft<R, DIR>(v[q]);
+            if constexpr (HALF_IN) dft_half_in<R, DIR>(v[q]);
+            else dft<R, DIR>(v[q]);
             if constexpr (TO_LDS) {
+                float2* dst = buf + Addr::idx(line, j * R);
 #pragma unroll
-                for (int r = 0; r < R; ++r) buf[Addr::idx(line, j * R + r)] = v[q][r];
+                for (int r = 0; r < R; ++r) dst[Addr::off(r)] = v[q][r];
             }
         }
     }
@@ -248,8 +289,9 @@ __device__ __forceinline__ void last_pass(float2* buf, const float2* __restrict_
         if (TOT % NT == 0 || b < TOT) {
             int line, j;
             Addr::template split<NB>(b, line, j);
+            const float2* src = buf + Addr::idx(line, j);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = buf[Addr::idx(line, j + r * NB)];
+            for (int r = 0; r < R; ++r) v[q][r] = src[Addr::off(r * NB)];
         }
     }
     if constexpr (SYNC_IO) __syncthreads();
@@ -506,7 +548,8 @@ __device__ __forceinline__ void single_pass(Src& src, Sink& sink) {
         if (TOT % NT == 0 || b < TOT) {
             int line, j;
             Addr::template split<1>(b, line, j);
-            dft<L, DIR>(v[q]);
+            if constexpr (HALF_IN && L >= 2) dft_half_in<L, DIR>(v[q]);
+            else dft<L, DIR>(v[q]);
 #pragma unroll
             for (int r = 0; r < ROUT; ++r) sink(line, r, v[q][r]);
         }

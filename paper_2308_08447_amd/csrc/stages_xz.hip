@@ -49,7 +49,7 @@ __device__ __forceinline__ void stage_table_n(float2* dst, const float2* __restr
 }
 
 __device__ __forceinline__ size_t t_index(int c, int kz, int NZ, int G, int ny, int kx, int y) {
-    return ((((size_t)c * NZ + kz) * G + (kx >> 2)) * ny + y) * TKB + (kx & 3);
+    return ((((size_t)c * NZ + kz) * G + kx / TKB) * ny + y) * TKB + kx % TKB;
 }
 
 // ============================================================================ xz forward
@@ -176,21 +176,36 @@ __global__ __launch_bounds__(NT) void yconv_kernel(const YCBatch b, const float2
     const int id = gid - b.start[item];
     const int kx = id % X1, kz = id / X1;
     const size_t cstride = (size_t)NZ * G * NY * TKB;  // complex elements per component
-    float2* __restrict__ col = d.T + (((size_t)kz * G + (kx >> 2)) * NY) * TKB + (kx & 3);
+    float2* __restrict__ col = d.T + (((size_t)kz * G + kx / TKB) * NY) * TKB + kx % TKB;
+
+    // The column's folded tensor values are loaded first, so that their latency
+    // overlaps the forward transform: slot s of a thread holds f = tid + s NT.
+    // K folded: ky > ny flips xy and yz, kz > nz flips xz and yz.
+    const int kzf = 2 * kz > NZ ? NZ - kz : kz;
+    const float sz = 2 * kz > NZ ? -1.f : 1.f;
+    const size_t KC = (size_t)Z1 * X1 * Y1;
+    const float* kp = d.K + ((size_t)kzf * X1 + kx) * Y1;
+    constexpr int NKS = (NY + 1 + NT - 1) / NT;
+    float kv[NKS][6];
+#pragma unroll
+    for (int s = 0; s < NKS; ++s) {
+        const int f = threadIdx.x + s * NT;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) kv[s][a] = f <= NY ? kp[a * KC + f] : 0.f;
+    }
 
     auto src = [&](int c, int yy) { return col[c * cstride + (size_t)yy * TKB]; };
     auto to_lds = [&](int c, int k, float2 v) { buf[c * LS + lpad(k)] = v; };
     fft_io<LNY, -1, 3, NT, Rows, true, false, true>(buf, tw, src, to_lds);
     __syncthreads();
 
-    // H^_a = sum_b K_ab M^_b, K folded: ky > ny flips xy and yz, kz > nz flips xz and yz
-    const int kzf = 2 * kz > NZ ? NZ - kz : kz;
-    const float sz = 2 * kz > NZ ? -1.f : 1.f;
-    const size_t KC = (size_t)Z1 * X1 * Y1;
-    const float* kp = d.K + ((size_t)kzf * X1 + kx) * Y1;
-    for (int f = threadIdx.x; f <= NY; f += NT) {
-        const float kxx = kp[f], kyy = kp[KC + f], kzz = kp[2 * KC + f];
-        const float kxy0 = kp[3 * KC + f], kxz = sz * kp[4 * KC + f], kyz0 = sz * kp[5 * KC + f];
+    // H^_a = sum_b K_ab M^_b; each folded value serves ky = f and its mirror LNY - f
+#pragma unroll
+    for (int s = 0; s < NKS; ++s) {
+        const int f = threadIdx.x + s * NT;
+        if (f > NY) continue;
+        const float kxx = kv[s][0], kyy = kv[s][1], kzz = kv[s][2];
+        const float kxy0 = kv[s][3], kxz = sz * kv[s][4], kyz0 = sz * kv[s][5];
         auto apply = [&](int ky, float sy) {
             const float kxy = sy * kxy0, kyz = sy * kyz0;
             float2 mx = buf[lpad(ky)], my = buf[LS + lpad(ky)], mz = buf[2 * LS + lpad(ky)];
@@ -310,6 +325,8 @@ bool xz_supported(int nx, int ny, int nz) {
     return pow2(nx) && pow2(ny) && pow2(nz) && nx >= 32 && nx <= 1024 && ny >= 16 && ny <= 512 &&
            nz <= 16;
 }
+
+int xz_groups(int X1) { return (X1 + TKB - 1) / TKB; }
 
 size_t xz_t_elems(int nx, int ny, int nz) {
     const int NZ = nz > 1 ? 2 * nz : 1;
