@@ -41,17 +41,24 @@ __device__ __forceinline__ void store3(float* __restrict__ f, size_t i, size_t N
 //   s=2: acc += 2 k3,   out = m + dt k3
 //   s=3: out = normalise(m + dt/6 (acc + k4))   (out may alias m)
 // One launch updates a batch of independent meshes (one descriptor each).
+// Blocks take 256-cell tiles of an xy plane with z fastest in the (XCD-renumbered)
+// block order, so the blocks of one tile at z-1, z, z+1 run together on one XCD
+// and read each other's planes from L2: the z neighbours of the exchange stencil
+// then cost no extra HBM traffic.
 __global__ __launch_bounds__(256) void llg_stage_kernel(const LLGBatch b, int stage) {
+    const int gid = xcd_tile(blockIdx.x, gridDim.x);
     int item = 0;
-    while (item + 1 < b.count && (int)blockIdx.x >= b.start[item + 1]) ++item;
+    while (item + 1 < b.count && gid >= b.start[item + 1]) ++item;
     const LLGDesc& a = b.d[item];
-    const size_t N = (size_t)a.nx * a.ny * a.nz;
-    size_t i = (size_t)(blockIdx.x - b.start[item]) * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+    const size_t P = (size_t)a.nx * a.ny;
+    const size_t N = P * a.nz;
+    const int local = gid - b.start[item];
+    const int zt = local % a.nz;
+    const size_t p = (size_t)(local / a.nz) * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const size_t i = (size_t)zt * P + p;
     const float* __restrict__ ms = a.ms;
-    int x = (int)(i % a.nx);
-    int y = (int)((i / a.nx) % a.ny);
-    int z = (int)(i / ((size_t)a.nx * a.ny));
+    const int x = (int)(p % a.nx), y = (int)(p / a.nx), z = zt;
     float3 c = load3(ms, i, N);
     // free boundaries: a missing neighbour is replaced by the cell itself
     float3 lap = make_float3(0.f, 0.f, 0.f);
@@ -181,8 +188,8 @@ int launch_llg_stage(LLGBatch b, int stage, hipStream_t stream) {
     if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "llg stage: bad batch size");
     b.start[0] = 0;
     for (int r = 0; r < b.count; ++r) {
-        size_t N = (size_t)b.d[r].nx * b.d[r].ny * b.d[r].nz;
-        b.start[r + 1] = b.start[r] + (int)blocks_for(N);
+        size_t P = (size_t)b.d[r].nx * b.d[r].ny;
+        b.start[r + 1] = b.start[r] + (int)blocks_for(P) * b.d[r].nz;
     }
     hipLaunchKernelGGL(llg_stage_kernel, dim3((unsigned)b.start[b.count]), dim3(256), 0, stream, b,
                        stage);

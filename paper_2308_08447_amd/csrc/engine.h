@@ -24,6 +24,17 @@ int fail(int code, const std::string& msg);
 #define DM_CHECK_LAUNCH() DM_HIP(hipGetLastError())
 
 // ---- geometry ---------------------------------------------------------------
+// Workgroups are dispatched to the 8 XCDs round-robin.  Renumber them so that
+// every XCD works on one contiguous range of tiles: neighbouring tiles, which
+// share cache lines of their partial-line segments (transposed rows, kernel
+// rows), then meet in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int B) {
+    constexpr int NXCD = 8;
+    int x = b % NXCD, i = b / NXCD;
+    int q = B / NXCD, r = B % NXCD;
+    return x * q + (x < r ? x : r) + i;
+}
+
 struct Geometry {
     int nx, ny, nz;        // cells
     int Nx, Ny, Nz;        // padded transform lengths (2n, or 1 when n = 1)

@@ -27,17 +27,6 @@ namespace dm {
 
 constexpr int NT = 256;
 
-// Workgroups are dispatched to the 8 XCDs round-robin.  Renumber them so that
-// every XCD works on one contiguous range of tiles: neighbouring tiles, which
-// share cache lines of their partial-line segments (transposed rows, kernel
-// rows), then meet in the same L2.
-__device__ __forceinline__ int xcd_tile(int b, int B) {
-    constexpr int NXCD = 8;
-    int x = b % NXCD, i = b / NXCD;
-    int q = B / NXCD, r = B % NXCD;
-    return x * q + (x < r ? x : r) + i;
-}
-
 // The two rows of a packed pair are adjacent in S1 (y fastest): move them as one
 // 16-byte access when both exist (rows are even then, so the address is aligned).
 __device__ __forceinline__ void store_pair(float2* d, float2 a, float2 b, int left) {

@@ -295,7 +295,8 @@ def test_llg_thin_film_one_step(gpu_lib, torch_dev):
 
 # ------------------------------------------------------------------ atomistic
 @pytest.mark.parametrize("n,macro,steps", [((16, 16, 8), 4, 1), ((16, 16, 8), 4, 5), ((8, 8, 8), 2, 3),
-                                           ((4, 4, 4), 4, 2)])
+                                           ((4, 4, 4), 4, 2), ((96, 24, 12), 3, 2), ((12, 6, 6), 3, 2),
+                                           ((256, 8, 4), 4, 1)])
 def test_atomistic_matches_oracle(gpu_lib, torch_dev, n, macro, steps):
     import paper_2308_08447_amd as pkg
     torch = torch_dev
