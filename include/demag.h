@@ -57,7 +57,16 @@ enum {
      * tensor product and all data stay FP32.  Same result definition and
      * tolerance as DEMAG_FP32. */
     DEMAG_BF16X2_MFMA = 1,    /* two-term split, 3 products per DFT step */
-    DEMAG_BF16X3_MFMA = 2     /* three-term split, 6 products per DFT step */
+    DEMAG_BF16X3_MFMA = 2,    /* three-term split, 6 products per DFT step */
+    /* May be or-ed with one of the above.  llg_step evaluates H_d once per RK4
+     * step, at the step start, and takes the values at the sub-steps
+     * (t + dt/2 twice, t + dt) from the quartic in time through the five most
+     * recent step-start fields: the polynomial extrapolation of the
+     * demagnetizing field of Sec. III (quartic for RK4).  The first five steps
+     * of a trajectory, and every step after a change of dt, evaluate all four
+     * stages.  The history (5 x 12 N bytes) lives in the plan and is allocated
+     * on the first llg_step; llg_reset discards it. */
+    DEMAG_EXTRAPOLATE_HD = 8
 };
 
 /* Mesh of n_x x n_y x n_z rectangular cells of size dx x dy x dz (m). */
@@ -75,7 +84,8 @@ typedef struct demag_plan demag_plan;   /* opaque; owns N^ and the FFT workspace
  * real components in FP32 packed by the y and z symmetries, and allocates the
  * FFT workspace.
  *   mesh    in   mesh description (copied).
- *   flags   in   DEMAG_FP32, DEMAG_BF16X2_MFMA or DEMAG_BF16X3_MFMA (one of them).
+ *   flags   in   DEMAG_FP32, DEMAG_BF16X2_MFMA or DEMAG_BF16X3_MFMA (one of them),
+ *                optionally or-ed with DEMAG_EXTRAPOLATE_HD.
  *   stream  in   hipStream_t used for the set-up kernels; the call synchronises it.
  *   out     out  receives the new plan (NULL on failure).
  * Errors: EINVAL (null/invalid mesh), EUNSUPPORTED (size), ENOMEM, EHIP.
@@ -126,6 +136,14 @@ typedef struct {
  */
 int llg_step(demag_plan* plan, float* m, const llg_params* params, double dt,
              int32_t nsteps, void* stream);
+
+/*
+ * llg_reset -- discard the H_d history of a DEMAG_EXTRAPOLATE_HD plan, so that
+ * the next llg_step starts a new trajectory (call it after setting m to a state
+ * that does not continue the previous steps).  No effect on other plans.
+ * Errors: EINVAL (NULL plan).
+ */
+int llg_reset(demag_plan* plan);
 
 /* ---- atomistic spin dynamics (Eqs. 7, 9, 10; Sec. IV) ------------------- */
 typedef struct {

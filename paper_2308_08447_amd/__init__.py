@@ -24,13 +24,14 @@ DEMAG_EBUSY = -5
 DEMAG_FP32 = 0
 DEMAG_BF16X2_MFMA = 1   # radix-16 passes as 2-term split BF16 MFMA products
 DEMAG_BF16X3_MFMA = 2   # 3-term split
+DEMAG_EXTRAPOLATE_HD = 8  # one H_d per RK4 step, quartic extrapolation at the sub-steps
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EUNSUPPORTED", -4: "EHIP", -5: "EBUSY"}
 
 # symbols declared in include/demag.h
 EXPORTS = (
     "demag_setup", "demag_field", "demag_plan_bytes", "demag_get_kernel", "demag_destroy",
-    "llg_step", "atom_setup", "atom_step", "atom_destroy", "demag_timing_enable",
+    "llg_step", "llg_reset", "atom_setup", "atom_step", "atom_destroy", "demag_timing_enable",
     "demag_timing_read", "demag_autotune", "demag_set_variant", "demag_get_variant",
     "demag_set_chunks", "demag_get_chunks", "demag_get_form", "serve_open", "serve_submit", "serve_wait",
     "serve_get_stats", "serve_close", "demag_last_error",
@@ -102,6 +103,7 @@ def load(path=None):
         "demag_get_kernel": ([vp, vp, sz, vp], ctypes.c_int),
         "demag_destroy": ([vp], ctypes.c_int),
         "llg_step": ([vp, vp, P(llg_params), ctypes.c_double, ctypes.c_int32, vp], ctypes.c_int),
+        "llg_reset": ([vp], ctypes.c_int),
         "atom_setup": ([P(atom_mesh), ctypes.c_uint32, vp, P(vp)], ctypes.c_int),
         "atom_step": ([vp, vp, P(atom_params), ctypes.c_double, ctypes.c_int32, vp], ctypes.c_int),
         "atom_destroy": ([vp], ctypes.c_int),
@@ -191,6 +193,10 @@ def llg_step(plan, m, params, dt, nsteps, stream=None):
         Ms, A, alpha, gamma, hz = params
         params = llg_params(Ms, A, alpha, gamma, (ctypes.c_double * 3)(*hz))
     return _check(load().llg_step(plan, _ptr(m), ctypes.byref(params), dt, nsteps, _stream(stream)))
+
+
+def llg_reset(plan):
+    return _check(load().llg_reset(plan))
 
 
 def demag_timing_enable(plan, max_records):

@@ -148,7 +148,7 @@ int s2_planes(const Geometry& g) {
 }
 
 bool uses_xz(const Geometry& g, uint32_t flags) {
-    return flags == DEMAG_FP32 && xz_supported(g.nx, g.ny, g.nz);
+    return (flags & ~(uint32_t)DEMAG_EXTRAPOLATE_HD) == DEMAG_FP32 && xz_supported(g.nx, g.ny, g.nz);
 }
 
 size_t workspace_bytes(const Geometry& g, uint32_t flags) {
@@ -185,6 +185,7 @@ void free_plan(demag_plan* p) {
     if (p->S2 != p->S1) (void)hipFree(p->S2);
     (void)hipFree(p->T);
     (void)hipFree(p->rk);
+    (void)hipFree(p->hist);
     delete p;
 }
 
@@ -200,7 +201,7 @@ int create_plan(const demag_mesh* mesh, uint32_t flags, hipStream_t s, demag_pla
     p->dy = mesh->dy;
     p->dz = mesh->dz;
     p->flags = flags;
-    p->mf = (flags & DEMAG_BF16X3_MFMA) ? 3 : (flags & DEMAG_BF16X2_MFMA) ? 2 : 0;
+    p->mf = (flags & 3) == DEMAG_BF16X3_MFMA ? 3 : (flags & 3) == DEMAG_BF16X2_MFMA ? 2 : 0;
     (void)hipGetDevice(&p->device);
     auto bail = [&](int code) {
         free_plan(p);
@@ -426,7 +427,7 @@ int run_fields(demag_plan* const* plans, const float* const* M, float* const* H,
     return DEMAG_OK;
 }
 
-static LLGDesc llg_desc(const LLGStep& st, const float* ms, float* out) {
+static LLGDesc llg_desc(const LLGStep& st, const float* ms, float* out, const float* Hd = nullptr) {
     const demag_plan* p = st.plan;
     const Geometry& g = p->g;
     const size_t n3 = 3 * g.cells();
@@ -435,7 +436,7 @@ static LLGDesc llg_desc(const LLGStep& st, const float* ms, float* out) {
     LLGDesc d;
     d.m = st.m;
     d.ms = ms;
-    d.Hd = p->rk;
+    d.Hd = Hd ? Hd : p->rk;
     d.acc = p->rk + 3 * n3;
     d.out = out;
     d.nx = g.nx;
@@ -451,8 +452,76 @@ static LLGDesc llg_desc(const LLGStep& st, const float* ms, float* out) {
     return d;
 }
 
+// Lagrange weights at t_n + theta dt of the quartic through t_n, t_n - dt, ..., t_n - 4 dt.
+static void quartic_weights(double theta, float w[5]) {
+    for (int j = 0; j < 5; ++j) {
+        double v = 1.0;
+        for (int k = 0; k < 5; ++k)
+            if (k != j) v *= (theta + k) / (double)(k - j);
+        w[j] = (float)v;
+    }
+}
+
+// One RK4 step of a DEMAG_EXTRAPOLATE_HD plan: H_d evaluated at the step start
+// into the history ring; once five entries exist, the sub-step fields come
+// from the quartic through them (theta = 1/2 for stages 2 and 3, 1 for stage 4).
+static int rk4_step_extrapolated(const LLGStep& st, hipStream_t s) {
+    demag_plan* p = st.plan;
+    int rc;
+    if ((rc = ensure_rk(p))) return rc;
+    const size_t n3 = 3 * p->g.cells();
+    if (!p->hist && (rc = dev_alloc((void**)&p->hist, 5 * n3 * sizeof(float), "H_d history")))
+        return rc;
+    if (p->hist_dt != st.dt) {
+        p->hist_n = 0;
+        p->hist_dt = st.dt;
+    }
+    float* A = p->rk + n3;
+    float* B = p->rk + 2 * n3;
+    float* Hx = p->rk;  // extrapolated or evaluated sub-step field
+    const float scale = (float)st.prm.Ms;
+    const int head = (p->hist_head + 4) % 5;  // the oldest slot takes the new field
+    float* H0 = p->hist + head * n3;
+    const float* in[4] = {st.m, A, B, A};
+    float* out[4] = {A, B, A, st.m};
+    const int nhist = p->hist_n + 1 < 5 ? p->hist_n + 1 : 5;
+    const float* hs[5];
+    for (int j = 0; j < 5; ++j) hs[j] = p->hist + ((head + j) % 5) * n3;
+    for (int stage = 0; stage < 4; ++stage) {
+        const float* Hd = Hx;
+        if (stage == 0) {
+            if ((rc = run_fields(&p, &in[0], &H0, &scale, 1, s))) return rc;
+            Hd = H0;
+        } else if (nhist < 5) {
+            if ((rc = run_fields(&p, &in[stage], &Hx, &scale, 1, s))) return rc;
+        } else if (stage != 2) {  // stage 2 re-uses the theta = 1/2 field of stage 1
+            float w[5];
+            quartic_weights(stage == 1 ? 0.5 : 1.0, w);
+            if ((rc = launch_extrapolate(Hx, hs, w, n3, s))) return rc;
+        }
+        LLGBatch b;
+        b.count = 1;
+        b.d[0] = llg_desc(st, in[stage], out[stage], Hd);
+        StageTimer t(p, DEMAG_STAGE_LLG, s);
+        if ((rc = launch_llg_stage(b, stage, s))) return rc;
+    }
+    p->hist_head = head;
+    p->hist_n = nhist;
+    return DEMAG_OK;
+}
+
 int rk4_step_batch(const LLGStep* steps, int n, hipStream_t s) {
     int rc;
+    bool extrap = false;
+    for (int i = 0; i < n; ++i) extrap = extrap || (steps[i].plan->flags & DEMAG_EXTRAPOLATE_HD);
+    if (extrap) {  // plans with a history advance one by one
+        for (int i = 0; i < n; ++i) {
+            if (steps[i].plan->flags & DEMAG_EXTRAPOLATE_HD) rc = rk4_step_extrapolated(steps[i], s);
+            else rc = rk4_step_batch(&steps[i], 1, s);
+            if (rc) return rc;
+        }
+        return DEMAG_OK;
+    }
     for (int i = 0; i < n; ++i)
         if ((rc = ensure_rk(steps[i].plan))) return rc;
     std::vector<demag_plan*> plans(n);
@@ -514,7 +583,8 @@ struct atom_plan {
 };
 
 static bool valid_flags(uint32_t flags) {
-    return flags == DEMAG_FP32 || flags == DEMAG_BF16X2_MFMA || flags == DEMAG_BF16X3_MFMA;
+    const uint32_t prec = flags & ~(uint32_t)DEMAG_EXTRAPOLATE_HD;
+    return prec == DEMAG_FP32 || prec == DEMAG_BF16X2_MFMA || prec == DEMAG_BF16X3_MFMA;
 }
 
 extern "C" {
@@ -574,6 +644,12 @@ int llg_step(demag_plan* plan, float* m, const llg_params* prm, double dt, int32
     LLGStep st{plan, m, *prm, dt};
     for (int step = 0; step < nsteps; ++step)
         if ((rc = rk4_step_batch(&st, 1, (hipStream_t)stream))) return rc;
+    return DEMAG_OK;
+}
+
+int llg_reset(demag_plan* plan) {
+    if (!plan) return fail(DEMAG_EINVAL, "plan is NULL");
+    plan->hist_n = 0;
     return DEMAG_OK;
 }
 

@@ -94,6 +94,22 @@ __global__ __launch_bounds__(256) void llg_stage_kernel(const LLGBatch b, int st
     }
 }
 
+// Sub-step demagnetizing field from the history ring: out = sum_j w_j h_j with
+// the weights of the polynomial through the five step-start fields.
+struct Extrap5 {
+    const float* h[5];
+    float w[5];
+};
+__global__ __launch_bounds__(256) void extrapolate_kernel(float* __restrict__ out, const Extrap5 e,
+                                                          size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float v = e.w[0] * e.h[0][i];
+#pragma unroll
+    for (int j = 1; j < 5; ++j) v = fmaf(e.w[j], e.h[j][i], v);
+    out[i] = v;
+}
+
 // ---------------------------------------------------------------- atomistic
 // Eq. (9): M = mu_s mu_B/(a^3 N_S) * sum of the unit spins of the macrocell.
 __global__ __launch_bounds__(256) void macro_average_kernel(AtomArgs a, const float* __restrict__ S,
@@ -193,6 +209,18 @@ int launch_llg_stage(LLGBatch b, int stage, hipStream_t stream) {
     }
     hipLaunchKernelGGL(llg_stage_kernel, dim3((unsigned)b.start[b.count]), dim3(256), 0, stream, b,
                        stage);
+    DM_CHECK_LAUNCH();
+    return DEMAG_OK;
+}
+
+int launch_extrapolate(float* out, const float* const h[5], const float w[5], size_t n,
+                       hipStream_t stream) {
+    Extrap5 e;
+    for (int j = 0; j < 5; ++j) {
+        e.h[j] = h[j];
+        e.w[j] = w[j];
+    }
+    hipLaunchKernelGGL(extrapolate_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, out, e, n);
     DM_CHECK_LAUNCH();
     return DEMAG_OK;
 }

@@ -135,6 +135,9 @@ struct LLGDesc {           // one mesh in a batched RK4 stage update
 };
 using LLGBatch = StageBatch<LLGDesc>;
 int launch_llg_stage(LLGBatch b, int stage, hipStream_t stream);
+// out = sum_j w[j] h[j] over n floats (polynomial extrapolation of a field)
+int launch_extrapolate(float* out, const float* const h[5], const float w[5], size_t n,
+                       hipStream_t stream);
 
 struct AtomArgs {
     int nx, ny, nz, macro;

@@ -55,6 +55,10 @@ struct demag_plan {
     int xc = 1;             // kx planes S2 holds
     int nch = 1;            // chunks the y/z stages are split into (>= ceil(X1 / xc))
     float* rk = nullptr;    // RK4 buffers (lazily allocated): H, A, B, acc, each 3 N floats
+    float* hist = nullptr;  // DEMAG_EXTRAPOLATE_HD: ring of 5 step-start H_d fields (3 N each)
+    int hist_n = 0;         // valid entries (<= 5)
+    int hist_head = 0;      // slot of the newest entry
+    double hist_dt = 0.0;   // step of the recorded trajectory
     int device = 0;
     int timing_cap = 0;     // per-stage event timing (demag_timing_enable)
     std::vector<hipEvent_t> ev[DEMAG_NSTAGES];

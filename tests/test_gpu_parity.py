@@ -293,6 +293,93 @@ def test_llg_thin_film_one_step(gpu_lib, torch_dev):
     assert err <= 1e-3
 
 
+# ------------------------------------------------------------------ H_d extrapolation
+def _extrap_run(pkg, torch, n, flags, m0, params, dt, chunks):
+    plan = pkg.demag_setup(n + W.CELL_4NM, flags)
+    try:
+        m = torch.from_numpy(m0).cuda()
+        for k in chunks:   # several llg_step calls: the history persists between them
+            pkg.llg_step(plan, m, params, dt, k)
+        torch.cuda.synchronize()
+        return m.cpu().numpy()
+    finally:
+        pkg.demag_destroy(plan)
+
+
+@pytest.mark.parametrize("n,flags,chunks", [((64, 32, 4), 8, (3, 9)), ((16, 16, 8), 8, (10,)),
+                                            ((128, 64, 2), 8, (5, 1, 4)), ((32, 32, 4), 8 | 2, (9,))],
+                         ids=["64x32x4", "16x16x8-fivepass", "128x64x2", "32x32x4-bf16x3"])
+def test_llg_extrapolated_matches_oracle(gpu_lib, torch_dev, n, flags, chunks):
+    """One H_d per RK4 step, quartic extrapolation at the sub-steps after five steps."""
+    import paper_2308_08447_amd as pkg
+    _say("extrapolated llg parity", n, flags, chunks)
+    m0 = W.unit_vectors((n[2], n[1], n[0]), seed=31)
+    alpha, dt, Hz = 0.02, 1e-13, (1e4, -2e4, 3e4)
+    params = (W.MS, W.A_EX, alpha, ollg.GAMMA, Hz)
+    got = _extrap_run(pkg, torch_dev, n, flags, m0, params, dt, chunks).astype(np.float64)
+    prob = ollg.LLGExtrapolated(n, W.CELL_4NM, W.MS, W.A_EX, alpha, Hzee=Hz)
+    ref = prob.run(m0.astype(np.float64), dt, sum(chunks))
+    err = odemag.rel_l2(got, ref)
+    _say("  rel-L2 of m", err, " of the increment", odemag.rel_l2(got - m0, ref - m0))
+    assert err <= TOL
+    assert odemag.rel_l2(got - m0, ref - m0) <= 1e-3
+
+
+def test_llg_reset_and_step_change(gpu_lib, torch_dev):
+    """llg_reset starts a new trajectory (same bits as a fresh plan); a new dt
+    restarts the history like the oracle does."""
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    n = (64, 32, 4)
+    params = (W.MS, W.A_EX, 0.05, ollg.GAMMA, (0.0, 0.0, 2e4))
+    mA = W.unit_vectors((4, 32, 64), seed=41)
+    mB = W.unit_vectors((4, 32, 64), seed=42)
+    plan = pkg.demag_setup(n + W.CELL_4NM, pkg.DEMAG_EXTRAPOLATE_HD)
+    try:
+        m = torch.from_numpy(mA).cuda()
+        pkg.llg_step(plan, m, params, 1e-13, 7)
+        pkg.llg_reset(plan)
+        m = torch.from_numpy(mB).cuda()
+        pkg.llg_step(plan, m, params, 1e-13, 8)
+        torch.cuda.synchronize()
+        after_reset = m.cpu().numpy()
+    finally:
+        pkg.demag_destroy(plan)
+    fresh = _extrap_run(pkg, torch, n, pkg.DEMAG_EXTRAPOLATE_HD, mB, params, 1e-13, (8,))
+    assert np.array_equal(after_reset, fresh)
+    # dt change: 6 steps of 1e-13 then 7 of 5e-14
+    plan = pkg.demag_setup(n + W.CELL_4NM, pkg.DEMAG_EXTRAPOLATE_HD)
+    try:
+        m = torch.from_numpy(mA).cuda()
+        pkg.llg_step(plan, m, params, 1e-13, 6)
+        pkg.llg_step(plan, m, params, 5e-14, 7)
+        torch.cuda.synchronize()
+        got = m.cpu().numpy().astype(np.float64)
+    finally:
+        pkg.demag_destroy(plan)
+    prob = ollg.LLGExtrapolated(n, W.CELL_4NM, W.MS, W.A_EX, 0.05, Hzee=(0.0, 0.0, 2e4))
+    ref = prob.run(prob.run(mA.astype(np.float64), 1e-13, 6), 5e-14, 7)
+    assert odemag.rel_l2(got, ref) <= TOL
+
+
+def test_llg_extrapolated_thin_film(gpu_lib, torch_dev):
+    """512x512x16 thin film (A = 1.3e-11, alpha = 0.02, dt = 1e-13): 7 steps, the
+    last two with extrapolated sub-step fields."""
+    import paper_2308_08447_amd as pkg
+    cfg = W.THIN_FILM
+    n = cfg["n"]
+    _say("extrapolated llg 512x512x16, 7 steps")
+    m0 = W.unit_vectors((n[2], n[1], n[0]), seed=0)
+    params = (cfg["Ms"], cfg["A"], cfg["alpha"], ollg.GAMMA, (0, 0, 0))
+    got = _extrap_run(pkg, torch_dev, n, pkg.DEMAG_EXTRAPOLATE_HD, m0, params, cfg["dt"], (7,))
+    prob = ollg.LLGExtrapolated(n, cfg["cell"], cfg["Ms"], cfg["A"], cfg["alpha"], workers=8)
+    ref = prob.run(m0.astype(np.float64), cfg["dt"], 7)
+    d_err = odemag.rel_l2(got.astype(np.float64) - m0, ref - m0)
+    _say("  rel-L2 of m", odemag.rel_l2(got.astype(np.float64), ref), " of the increment", d_err)
+    assert odemag.rel_l2(got.astype(np.float64), ref) <= TOL
+    assert d_err <= 1e-3
+
+
 # ------------------------------------------------------------------ atomistic
 @pytest.mark.parametrize("n,macro,steps", [((16, 16, 8), 4, 1), ((16, 16, 8), 4, 5), ((8, 8, 8), 2, 3),
                                            ((4, 4, 4), 4, 2), ((96, 24, 12), 3, 2), ((12, 6, 6), 3, 2),

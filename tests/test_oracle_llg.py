@@ -139,3 +139,51 @@ def test_atomistic_demag_is_macrocell_demag():
     Hm = demag.demag_direct(Mm, (h, h, h))
     np.testing.assert_allclose(H[:, ::macro, ::macro, ::macro], Hm, rtol=1e-10, atol=1e-6)
     np.testing.assert_allclose(H[:, 1::macro, 1::macro, 1::macro], Hm, rtol=1e-10, atol=1e-6)
+
+
+# ---------------------------------------------------------------- H_d extrapolation
+def test_quartic_extrapolation_is_exact_for_quartics_only():
+    """The sub-step field is the degree-4 polynomial through five step-start values:
+    exact for any polynomial of degree <= 4 in time, not for degree 5."""
+    rng = np.random.default_rng(4)
+    for deg in (0, 2, 3, 4):
+        c = rng.standard_normal((deg + 1, 3, 2, 2))
+        F = lambda s: sum(c[k] * s ** k for k in range(deg + 1))
+        hist = [F(-j) for j in range(5)]
+        for theta in (0.5, 1.0, 2.5):
+            np.testing.assert_allclose(llg.quartic_extrapolate(hist, theta), F(theta), rtol=0, atol=1e-10)
+    F5 = lambda s: s ** 5
+    assert abs(float(llg.quartic_extrapolate([F5(-j) for j in range(5)], 1.0)) - 1.0) > 1.0
+    # one step ahead the weights are the binomial ones 5, -10, 10, -5, 1
+    e = np.eye(5)
+    w = [float(llg.quartic_extrapolate(list(e[j]), 1.0)) for j in range(5)]
+    np.testing.assert_allclose(w, [5, -10, 10, -5, 1], atol=1e-9)
+
+
+def test_extrapolated_rk4_starts_as_plain_rk4():
+    n = (8, 8, 2)
+    m0 = W.unit_vectors((2, 8, 8), 3).astype(np.float64)
+    a = llg.LLG(n, W.CELL_4NM, W.MS, W.A_EX, 0.02).run(m0, 1e-13, 4)
+    b = llg.LLGExtrapolated(n, W.CELL_4NM, W.MS, W.A_EX, 0.02).run(m0, 1e-13, 4)
+    np.testing.assert_allclose(b, a, rtol=0, atol=1e-13)
+
+
+def test_extrapolated_rk4_keeps_fourth_order():
+    """Against a fine-step plain RK4 reference, the error of RK4 with quartic H_d
+    extrapolation falls ~16x per halving of dt and stays within 2x of plain RK4
+    (the extrapolation costs no accuracy order)."""
+    n = (16, 16, 2)
+    m0 = W.unit_vectors((2, 16, 16), 3).astype(np.float64)
+    T = 8e-12
+    ref = llg.LLG(n, W.CELL_4NM, W.MS, W.A_EX, 0.02).run(m0, T / 640, 640)
+    scale = np.linalg.norm(ref - m0)
+    errs = []
+    for dt in (4e-13, 2e-13, 1e-13):
+        ns = int(round(T / dt))
+        plain = llg.LLG(n, W.CELL_4NM, W.MS, W.A_EX, 0.02).run(m0, dt, ns)
+        extr = llg.LLGExtrapolated(n, W.CELL_4NM, W.MS, W.A_EX, 0.02).run(m0, dt, ns)
+        e_plain = np.linalg.norm(plain - ref) / scale
+        e_extr = np.linalg.norm(extr - ref) / scale
+        assert e_extr <= 2.0 * e_plain, (dt, e_extr, e_plain)
+        errs.append(e_extr)
+    assert errs[0] / errs[1] > 10 and errs[1] / errs[2] > 10, errs
