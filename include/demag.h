@@ -66,7 +66,14 @@ enum {
      * of a trajectory, and every step after a change of dt, evaluate all four
      * stages.  The history (5 x 12 N bytes) lives in the plan and is allocated
      * on the first llg_step; llg_reset discards it. */
-    DEMAG_EXTRAPOLATE_HD = 8
+    DEMAG_EXTRAPOLATE_HD = 8,
+    /* May be or-ed with the others.  The kernel is the point-dipole tensor of
+     * Eq. (8), N_ab(r) = V (delta_ab |r|^2 - 3 r_a r_b) / (4 pi |r|^5) with
+     * N(0) = 0 and V = dx dy dz, instead of the cell-averaged tensor: with
+     * M = mu_B mu_S S^ / V per lattice site, demag_field returns the lattice
+     * dipole-dipole field of Eq. (8) (an atom plan with macro = 1 and this
+     * flag steps the full dipole-dipole interaction). */
+    DEMAG_POINT_DIPOLE = 16
 };
 
 /* Mesh of n_x x n_y x n_z rectangular cells of size dx x dy x dz (m). */
@@ -85,7 +92,7 @@ typedef struct demag_plan demag_plan;   /* opaque; owns N^ and the FFT workspace
  * FFT workspace.
  *   mesh    in   mesh description (copied).
  *   flags   in   DEMAG_FP32, DEMAG_BF16X2_MFMA or DEMAG_BF16X3_MFMA (one of them),
- *                optionally or-ed with DEMAG_EXTRAPOLATE_HD.
+ *                optionally or-ed with DEMAG_EXTRAPOLATE_HD and DEMAG_POINT_DIPOLE.
  *   stream  in   hipStream_t used for the set-up kernels; the call synchronises it.
  *   out     out  receives the new plan (NULL on failure).
  * Errors: EINVAL (null/invalid mesh), EUNSUPPORTED (size), ENOMEM, EHIP.

@@ -62,14 +62,16 @@ class Atomistic:
     """Spins n = (nx, ny, nz) on a simple-cubic lattice of constant a (m)."""
 
     def __init__(self, n, a, macro, J, mu_s, alpha, gamma=llg.GAMMA,
-                 Hzee=(0.0, 0.0, 0.0), workers=None):
+                 Hzee=(0.0, 0.0, 0.0), workers=None, kind="newell"):
         self.n = tuple(int(v) for v in n)
         self.a, self.macro = float(a), int(macro)
         self.J, self.mu_s, self.alpha, self.gamma = float(J), float(mu_s), float(alpha), float(gamma)
         self.Hzee = np.asarray(Hzee, dtype=np.float64).reshape(3, 1, 1, 1)
         nm = tuple(v // self.macro for v in self.n)
         h = self.macro * self.a
-        self.demag = demag.DemagFFT(nm, (h, h, h), workers)
+        # kind "newell": demagnetizing field of the macrocells (Eq. 9 into Eq. 1);
+        # kind "dipole" with macro = 1: the lattice dipole-dipole field of Eq. (8)
+        self.demag = demag.DemagFFT(nm, (h, h, h), workers, kind)
 
     def field(self, S):
         Hd = self.demag(macro_average(S, self.macro, self.a, self.mu_s))

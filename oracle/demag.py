@@ -17,7 +17,17 @@ Arrays are laid out (component, z, y, x), x fastest, SI units (A/m).
 import numpy as np
 import scipy.fft as sfft
 
-from . import newell
+from . import dipole, newell
+
+
+def _tensor_fn(kind):
+    """Kernel of the convolution: the cell-averaged (Newell) tensor of Eq. (1),
+    or the point-dipole tensor of Eq. (8) (kind "dipole")."""
+    if kind == "newell":
+        return newell.tensor
+    if kind == "dipole":
+        return dipole.tensor
+    raise ValueError(kind)
 
 
 def padded_size(n):
@@ -31,14 +41,19 @@ def tensor3(Nc):
     return ((xx, xy, xz), (xy, yy, yz), (xz, yz, zz))
 
 
-def demag_direct(M, cell):
+def demag_direct(M, cell, kind="newell"):
     """H_i = -sum_j N(i - j) M_j by explicit summation (small meshes only).
 
     M: float array (3, nz, ny, nx) in A/m.  Returns H with the same shape.
     """
     M = np.asarray(M, dtype=np.float64)
     _, nz, ny, nx = M.shape
-    grid = newell.tensor_grid((nx, ny, nz), cell)  # (6, 2nz-1, 2ny-1, 2nx-1)
+    if kind == "newell":
+        grid = newell.tensor_grid((nx, ny, nz), cell)  # (6, 2nz-1, 2ny-1, 2nx-1)
+    else:
+        kk, jj, ii = np.meshgrid(np.arange(-nz + 1, nz), np.arange(-ny + 1, ny),
+                                 np.arange(-nx + 1, nx), indexing="ij")
+        grid = _tensor_fn(kind)(ii, jj, kk, cell)
     kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     src_k, src_j, src_i = kk.ravel(), jj.ravel(), ii.ravel()
     Mflat = M.reshape(3, -1)
@@ -73,7 +88,7 @@ class DemagFFT:
     initialisation stage, Sec. II).
     """
 
-    def __init__(self, n, cell, workers=None):
+    def __init__(self, n, cell, workers=None, kind="newell"):
         self.n = tuple(int(v) for v in n)  # (nx, ny, nz)
         self.cell = tuple(float(c) for c in cell)
         self.N = padded_size(self.n)  # (Nx, Ny, Nz)
@@ -81,7 +96,7 @@ class DemagFFT:
         nx, ny, nz = self.n
         Nx, Ny, Nz = self.N
         kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-        octant = newell.tensor(ii, jj, kk, self.cell)  # (6, nz, ny, nx): r >= 0
+        octant = _tensor_fn(kind)(ii, jj, kk, self.cell)  # (6, nz, ny, nx): r >= 0
         ax, sx, ux = _axis_map(nx, Nx)
         ay, sy, uy = _axis_map(ny, Ny)
         az, sz, uz = _axis_map(nz, Nz)
@@ -112,11 +127,11 @@ class DemagFFT:
         return H
 
 
-def demag_fft(M, cell, workers=None):
+def demag_fft(M, cell, workers=None, kind="newell"):
     """One-shot H_d by the zero-padded FFT convolution."""
     M = np.asarray(M, dtype=np.float64)
     _, nz, ny, nx = M.shape
-    return DemagFFT((nx, ny, nz), cell, workers)(M)
+    return DemagFFT((nx, ny, nz), cell, workers, kind)(M)
 
 
 def demag_at(M, cell, targets):

@@ -25,6 +25,7 @@ DEMAG_FP32 = 0
 DEMAG_BF16X2_MFMA = 1   # radix-16 passes as 2-term split BF16 MFMA products
 DEMAG_BF16X3_MFMA = 2   # 3-term split
 DEMAG_EXTRAPOLATE_HD = 8  # one H_d per RK4 step, quartic extrapolation at the sub-steps
+DEMAG_POINT_DIPOLE = 16   # point-dipole kernel of the lattice dipole-dipole field (Eq. 8)
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EUNSUPPORTED", -4: "EHIP", -5: "EBUSY"}
 

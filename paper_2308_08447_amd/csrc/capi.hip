@@ -75,15 +75,15 @@ Spectrum::~Spectrum() {
     if (K) (void)hipFree(K);
 }
 
-using SpecKey = std::tuple<int, int, int, int, double, double, double>;
+using SpecKey = std::tuple<int, int, int, int, double, double, double, int>;
 static std::mutex g_spec_mu;
 static std::map<SpecKey, std::weak_ptr<Spectrum>> g_spec;
 
-int get_spectrum(const Geometry& g, double dx, double dy, double dz, hipStream_t s,
+int get_spectrum(const Geometry& g, double dx, double dy, double dz, int kind, hipStream_t s,
                  std::shared_ptr<Spectrum>* out) {
     int dev = 0;
     (void)hipGetDevice(&dev);
-    SpecKey key{dev, g.nx, g.ny, g.nz, dx, dy, dz};
+    SpecKey key{dev, g.nx, g.ny, g.nz, dx, dy, dz, kind};
     std::lock_guard<std::mutex> lk(g_spec_mu);
     auto it = g_spec.find(key);
     if (it != g_spec.end()) {
@@ -97,10 +97,11 @@ int get_spectrum(const Geometry& g, double dx, double dy, double dz, hipStream_t
     sp->dx = dx;
     sp->dy = dy;
     sp->dz = dz;
+    sp->kind = kind;
     sp->device = dev;
     int rc = dev_alloc((void**)&sp->K, sp->bytes(), "kernel");
     if (rc) return rc;
-    rc = compute_kernel(g, dx, dy, dz, sp->K, s);
+    rc = compute_kernel(g, dx, dy, dz, kind, sp->K, s);
     if (rc) return rc;
     g_spec[key] = sp;
     *out = sp;
@@ -148,7 +149,7 @@ int s2_planes(const Geometry& g) {
 }
 
 bool uses_xz(const Geometry& g, uint32_t flags) {
-    return (flags & ~(uint32_t)DEMAG_EXTRAPOLATE_HD) == DEMAG_FP32 && xz_supported(g.nx, g.ny, g.nz);
+    return (flags & 3) == DEMAG_FP32 && xz_supported(g.nx, g.ny, g.nz);
 }
 
 size_t workspace_bytes(const Geometry& g, uint32_t flags) {
@@ -225,7 +226,8 @@ int create_plan(const demag_mesh* mesh, uint32_t flags, hipStream_t s, demag_pla
             p->S2 = p->S1;
         }
     }
-    if ((rc = get_spectrum(g, mesh->dx, mesh->dy, mesh->dz, s, &p->spec))) return bail(rc);
+    const int kind = (flags & DEMAG_POINT_DIPOLE) ? 1 : 0;
+    if ((rc = get_spectrum(g, mesh->dx, mesh->dy, mesh->dz, kind, s, &p->spec))) return bail(rc);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find({g.nx, g.ny, g.nz, p->mf});
@@ -583,7 +585,7 @@ struct atom_plan {
 };
 
 static bool valid_flags(uint32_t flags) {
-    const uint32_t prec = flags & ~(uint32_t)DEMAG_EXTRAPOLATE_HD;
+    const uint32_t prec = flags & ~(uint32_t)(DEMAG_EXTRAPOLATE_HD | DEMAG_POINT_DIPOLE);
     return prec == DEMAG_FP32 || prec == DEMAG_BF16X2_MFMA || prec == DEMAG_BF16X3_MFMA;
 }
 

@@ -116,7 +116,7 @@ void fill_twiddles(float2* host, int Lmax);
 
 // ---- N^ set-up (tensor.hip) ---------------------------------------------------
 // Computes the packed FP32 kernel K (device) for the geometry and cell, in FP64.
-int compute_kernel(const Geometry& g, double dx, double dy, double dz, float* K,
+int compute_kernel(const Geometry& g, double dx, double dy, double dz, int kind, float* K,
                    hipStream_t stream);
 
 // ---- dynamics (dynamics.hip) ----------------------------------------------------

@@ -16,6 +16,7 @@ namespace dm {
 struct Spectrum {
     Geometry g;
     double dx = 0, dy = 0, dz = 0;
+    int kind = 0;         // 0 cell-averaged (Eq. 1), 1 point dipole (Eq. 8)
     float* K = nullptr;   // [6][Z1][X1][Y1]
     int device = 0;
     ~Spectrum();
@@ -23,7 +24,7 @@ struct Spectrum {
 };
 
 // Looks the mesh up in the process-wide cache or computes it (FP64 on the GPU).
-int get_spectrum(const Geometry& g, double dx, double dy, double dz, hipStream_t s,
+int get_spectrum(const Geometry& g, double dx, double dy, double dz, int kind, hipStream_t s,
                  std::shared_ptr<Spectrum>* out);
 // Twiddle table of the current device (all lengths up to 4096), created once.
 int device_twiddles(const float2** out);

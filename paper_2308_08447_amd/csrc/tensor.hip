@@ -164,9 +164,11 @@ __device__ void tensor_far(double x, double y, double z, double hx, double hy, d
     }
 }
 
-// N(r) on the octant; T0[6][nz][ny][nx]
+// N(r) on the octant; T0[6][nz][ny][nx].  kind 0: the cell-averaged tensor of
+// Eq. (1) (Newell near, moment expansion far); kind 1: the point-dipole tensor of
+// Eq. (8), V (delta |r|^2 - 3 r r)/(4 pi |r|^5) with N(0) = 0 (site i excluded).
 __global__ void tensor_octant_kernel(double* __restrict__ T0, int nx, int ny, int nz,
-                                     double hx, double hy, double hz) {
+                                     double hx, double hy, double hz, int kind) {
     size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t n = (size_t)nx * ny * nz;
     if (idx >= n) return;
@@ -175,7 +177,16 @@ __global__ void tensor_octant_kernel(double* __restrict__ T0, int nx, int ny, in
     int k = (int)(idx / ((size_t)nx * ny));
     double X = i * hx, Y = j * hy, Z = k * hz;
     double out[6];
-    if (X * X + Y * Y + Z * Z <= RC * RC) {
+    const double r2 = X * X + Y * Y + Z * Z;
+    if (kind == 1) {
+        const double c = r2 > 0.0 ? hx * hy * hz / (4.0 * PI * r2 * r2 * sqrt(r2)) : 0.0;
+        out[0] = c * (r2 - 3.0 * X * X);
+        out[1] = c * (r2 - 3.0 * Y * Y);
+        out[2] = c * (r2 - 3.0 * Z * Z);
+        out[3] = c * (-3.0 * X * Y);
+        out[4] = c * (-3.0 * X * Z);
+        out[5] = c * (-3.0 * Y * Z);
+    } else if (r2 <= RC * RC) {
         double c = 1.0 / (4.0 * PI * hx * hy * hz);
         out[0] = c * stencil<true>(X, Y, Z, hx, hy, hz);
         out[1] = c * stencil<true>(Y, X, Z, hy, hx, hz);
@@ -266,7 +277,7 @@ struct DevBuf {
 
 }  // namespace
 
-int compute_kernel(const Geometry& g, double dx, double dy, double dz, float* K,
+int compute_kernel(const Geometry& g, double dx, double dy, double dz, int kind, float* K,
                    hipStream_t stream) {
     const int nx = g.nx, ny = g.ny, nz = g.nz, X1 = g.X1, Y1 = g.Y1, Z1 = g.Z1;
     const double h = std::fmax(dx, std::fmax(dy, dz));
@@ -295,7 +306,7 @@ int compute_kernel(const Geometry& g, double dx, double dy, double dz, float* K,
     const double* TR = (const double*)trig.p;
 
     hipLaunchKernelGGL(tensor_octant_kernel, dim3((unsigned)((n0 + 127) / 128)), dim3(128), 0,
-                       stream, (double*)T0.p, nx, ny, nz, dx / h, dy / h, dz / h);
+                       stream, (double*)T0.p, nx, ny, nz, dx / h, dy / h, dz / h, kind);
     DM_CHECK_LAUNCH();
 
     // parity (x, y, z) per component: xx yy zz xy xz yz

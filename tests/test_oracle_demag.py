@@ -95,3 +95,61 @@ def test_demag_at_matches_full_field():
     got = demag.demag_at(M, cell, targets)
     for t, (x, y, z) in enumerate(targets):
         np.testing.assert_allclose(got[:, t], H[:, z, y, x], rtol=1e-12, atol=1e-6)
+
+
+# ---------------------------------------------------------------- point-dipole kernel, Eq. (8)
+def test_dipole_field_vanishes_at_centre_of_uniform_cubic_lattice():
+    """Cubic symmetry: the lattice sum of (3 r r - r^2)/r^5 over a (2k+1)^3 cube
+    centred on a site is zero, whatever the (uniform) moment direction."""
+    from oracle import demag as od
+    for k in (1, 2, 3):
+        n = 2 * k + 1
+        M = np.zeros((3, n, n, n))
+        M[0], M[1], M[2] = 1.0, 0.3, -0.7
+        H = od.demag_fft(M, (1e-9, 1e-9, 1e-9), kind="dipole")
+        assert np.abs(H[:, k, k, k]).max() <= 1e-14 * np.abs(H).max()
+
+
+def test_dipole_field_of_a_chain_is_a_zeta_sum():
+    """A line of 2K+1 equal moments: at the middle site the field is
+    (1/4 pi) sum_{m != 0} (3 cos^2 - 1)/|m|^3 -> 4 zeta_K(3)/(4 pi) along the line
+    for moments along it, -2 zeta_K(3)/(4 pi) for moments across it (unit spacing,
+    unit moment density)."""
+    from oracle import demag as od
+    K = 120
+    n = 2 * K + 1
+    zeta = sum(1.0 / m ** 3 for m in range(1, K + 1))
+    M = np.zeros((3, 1, 1, n))
+    M[0] = 1.0
+    H = od.demag_fft(M, (1e-9, 1e-9, 1e-9), kind="dipole")
+    assert H[0, 0, 0, K] == pytest.approx(4 * zeta / (4 * np.pi), rel=1e-12)
+    M = np.zeros((3, 1, 1, n))
+    M[1] = 1.0
+    H = od.demag_fft(M, (1e-9, 1e-9, 1e-9), kind="dipole")
+    assert H[1, 0, 0, K] == pytest.approx(-2 * zeta / (4 * np.pi), rel=1e-12)
+
+
+def test_newell_tensor_tends_to_the_point_dipole():
+    """Far from the source, the cell-averaged tensor approaches the point-dipole
+    tensor: doubling the distance divides the relative difference by ~16 for
+    cubic cells (the h^2 term vanishes) and by ~4 otherwise."""
+    from oracle import dipole, newell
+
+    def rel(r, cell):
+        nw, dp = newell.tensor(*r, cell), dipole.tensor(*r, cell)
+        return np.abs(nw - dp).max() / np.abs(dp).max()
+
+    r1, r2 = (40, 30, 20), (80, 60, 40)
+    cub = rel(r1, (1, 1, 1)) / rel(r2, (1, 1, 1))
+    flat = rel(r1, (1.0, 0.7, 0.4)) / rel(r2, (1.0, 0.7, 0.4))
+    assert rel(r1, (1, 1, 1)) < 1e-7
+    assert 13 < cub < 19, cub
+    assert 3.5 < flat < 4.5, flat
+
+
+def test_dipole_fft_matches_direct_sum():
+    from oracle import demag as od
+    M = np.random.default_rng(2).standard_normal((3, 3, 4, 5))
+    cell = (1e-9, 2e-9, 1.5e-9)
+    np.testing.assert_allclose(od.demag_fft(M, cell, kind="dipole"), od.demag_direct(M, cell, kind="dipole"),
+                               rtol=0, atol=1e-12 * 1)
