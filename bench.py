@@ -160,6 +160,21 @@ def serve_bench(pkg, count, steps, loads, budget=16 << 30, max_active=64, seed=2
     mix = W.serve_requests(count, seed)
     reqs = [(n, a, steps, W.unit_vectors((n[2], n[1], n[0]), s % 1000003)) for n, a, s in mix]
     flags = pkg.SERVE_GRAPHS
+    # plain FP32 form for comparison: the same requests one after another through
+    # llg_step on one stream (a plan per request; N^ is shared per shape)
+    import torch
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cell_steps = 0
+    for n, a, nsteps, m0 in reqs:
+        plan = pkg.demag_setup(n + W.CELL_4NM, stream=stream)
+        m = torch.from_numpy(m0).cuda()
+        pkg.llg_step(plan, m, (W.MS, W.A_EX, a, 2.21276e5, (0.0, 0.0, 0.0)), 1e-13, nsteps, stream)
+        m.cpu()
+        pkg.demag_destroy(plan)
+        cell_steps += n[0] * n[1] * n[2] * nsteps
+    seq_wall = time.perf_counter() - t0
     # closed loop (everything queued at t = 0): saturated throughput
     wall, lat, st = serve_run(pkg, reqs, None, budget, max_active, flags)
     thr = count / wall
@@ -167,6 +182,8 @@ def serve_bench(pkg, count, steps, loads, budget=16 << 30, max_active=64, seed=2
            "max_active": max_active, "closed_loop_req_per_s": round(thr, 3),
            "closed_loop_cell_steps_per_s": round(st["cell_steps"] / wall, 1),
            "peak_GB": round(st["peak_bytes"] / 2**30, 2), "graph_captures": st["graph_captures"],
+           "sequential_plain_req_per_s": round(count / seq_wall, 3),
+           "sequential_plain_cell_steps_per_s": round(cell_steps / seq_wall, 1),
            "open_loop": []}
     for f in loads:
         wall, lat, st = serve_run(pkg, reqs, f * thr, budget, max_active, flags)
