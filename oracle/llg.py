@@ -4,8 +4,10 @@ infrastructure only).
 * Exchange field, Eq. (4) (Sec. III): H_ex = 2A/(mu0 Ms) * lap(m), with the
   7-point Laplacian sum_d (m[i+e_d] - 2 m[i] + m[i-e_d]) / h_d^2.  The paper
   states no boundary condition; free (Neumann) boundaries are taken: a missing
-  neighbour is replaced by m[i] itself, so it contributes nothing.  An axis with a
-  single cell contributes no term.
+  neighbour is replaced by m[i] itself, so it contributes nothing.  Along a
+  periodic axis (Sec. II, periodic boundary conditions) the neighbours wrap
+  around: the first and last cells are neighbours.  An axis with a single cell
+  contributes no term.
 * LLG, Eq. (5), rewritten in explicit Landau-Lifshitz form:
       dm/dt = -gamma/(1+alpha^2) * [m x H + alpha m x (m x H)].
 * Effective field (Sec. III): H_eff = H_d + H_ex + H_Zee (constant Zeeman).
@@ -28,19 +30,24 @@ a change of dt starts the history afresh (the nodes are dt apart).
 import numpy as np
 
 from . import demag
+from . import pbc as pbc_mod
 
 MU0 = 4e-7 * np.pi
 GAMMA = 2.21276e5  # mu0 * 1.76086e11, m/(A s)
 
 
-def exchange_field(m, cell, A, Ms):
-    """H_ex = 2A/(mu0 Ms) lap(m) with free boundaries; m is (3, nz, ny, nx)."""
+def exchange_field(m, cell, A, Ms, pbc=(False, False, False)):
+    """H_ex = 2A/(mu0 Ms) lap(m); m is (3, nz, ny, nx); free boundaries except
+    along the axes (x, y, z) flagged in pbc, which wrap around."""
     m = np.asarray(m, dtype=np.float64)
     dx, dy, dz = cell
     lap = np.zeros_like(m)
-    for axis, h in ((3, dx), (2, dy), (1, dz)):
+    for axis, h, per in ((3, dx, pbc[0]), (2, dy, pbc[1]), (1, dz, pbc[2])):
         n = m.shape[axis]
         if n == 1:
+            continue
+        if per:
+            lap += (np.roll(m, -1, axis) + np.roll(m, 1, axis) - 2.0 * m) / (h * h)
             continue
         fwd = np.zeros_like(m)  # m[i+1] - m[i], zero at the last cell
         bwd = np.zeros_like(m)  # m[i-1] - m[i], zero at the first cell
@@ -66,15 +73,22 @@ class LLG:
     """Thin-film LLG problem: mesh n = (nx, ny, nz), cell (dx, dy, dz) in m."""
 
     def __init__(self, n, cell, Ms, A, alpha, gamma=GAMMA, Hzee=(0.0, 0.0, 0.0),
-                 workers=None, demag_on=True):
+                 workers=None, demag_on=True, pbc=(False, False, False), images=None):
         self.n = tuple(int(v) for v in n)
         self.cell = tuple(float(c) for c in cell)
         self.Ms, self.A, self.alpha, self.gamma = float(Ms), float(A), float(alpha), float(gamma)
         self.Hzee = np.asarray(Hzee, dtype=np.float64).reshape(3, 1, 1, 1)
-        self.demag = demag.DemagFFT(self.n, self.cell, workers) if demag_on else None
+        self.pbc = tuple(bool(p) for p in pbc)
+        if not demag_on:
+            self.demag = None
+        elif any(self.pbc):
+            images = pbc_mod.DEFAULT_IMAGES if images is None else images
+            self.demag = pbc_mod.DemagPBC(self.n, self.cell, self.pbc, images, workers)
+        else:
+            self.demag = demag.DemagFFT(self.n, self.cell, workers)
 
     def field(self, m):
-        H = exchange_field(m, self.cell, self.A, self.Ms) + self.Hzee
+        H = exchange_field(m, self.cell, self.A, self.Ms, self.pbc) + self.Hzee
         if self.demag is not None:
             H = H + self.demag(self.Ms * m)
         return H
@@ -100,7 +114,7 @@ class LLG:
         """Exchange + demag + Zeeman energy (J) of the discrete system:
         E = -mu0 Ms V sum_i m_i . (H_ex/2 + H_d/2 + H_zee)."""
         V = float(np.prod(self.cell))
-        Hhalf = 0.5 * exchange_field(m, self.cell, self.A, self.Ms)
+        Hhalf = 0.5 * exchange_field(m, self.cell, self.A, self.Ms, self.pbc)
         if self.demag is not None:
             Hhalf = Hhalf + 0.5 * self.demag(self.Ms * m)
         Hhalf = Hhalf + self.Hzee
@@ -129,7 +143,7 @@ class LLGExtrapolated(LLG):
         self.history_dt = None
 
     def _field_with(self, m, Hd):
-        return exchange_field(m, self.cell, self.A, self.Ms) + self.Hzee + Hd
+        return exchange_field(m, self.cell, self.A, self.Ms, self.pbc) + self.Hzee + Hd
 
     def rk4_step(self, m, dt):
         m = np.asarray(m, dtype=np.float64)
