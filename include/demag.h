@@ -73,8 +73,29 @@ enum {
      * M = mu_B mu_S S^ / V per lattice site, demag_field returns the lattice
      * dipole-dipole field of Eq. (8) (an atom plan with macro = 1 and this
      * flag steps the full dipole-dipole interaction). */
-    DEMAG_POINT_DIPOLE = 16
+    DEMAG_POINT_DIPOLE = 16,
+    /* Periodic boundary conditions (Sec. II: a modified kernel and no zero
+     * padding along a periodic axis).  May be or-ed with DEMAG_FP32 (only) and
+     * the flags above; atom plans and the server take open meshes only.  Along
+     * a periodic axis d the transform has length n_d (circular convolution)
+     * and the tensor is the sum over the body's periodic images,
+     *   N_pbc(r) = sum_m N(r + m_x n_x dx e_x + m_y n_y dy e_y + m_z n_z dz e_z),
+     * |m_d| <= P on periodic axes (0 on open ones), P = DEMAG_PBC_IMAGES value
+     * (0: the mesh alone, folded), taken at the displacements
+     * r_d in (-n_d/2, n_d/2]; a component odd in d (N_xy odd in x and y, ...)
+     * is set to 0 at r_d = n_d/2, the value the infinite image sum has there.
+     * Images farther than 64 max(dx, dy, dz) use the moment expansion of the
+     * cell-pair tensor through its h^2 term (relative error below 1e-6 there).
+     * llg_step wraps the exchange stencil around periodic axes.  Set-up cost
+     * grows as (2P + 1)^(periodic axes) FP64 tensor evaluations per octant
+     * entry. */
+    DEMAG_PBC_X = 32,
+    DEMAG_PBC_Y = 64,
+    DEMAG_PBC_Z = 128
 };
+/* Image count P (0..255) of a periodic plan, in bits 8..15 of the flags. */
+#define DEMAG_PBC_IMAGES_SHIFT 8
+#define DEMAG_PBC_IMAGES(p) (((uint32_t)(p) & 0xffu) << DEMAG_PBC_IMAGES_SHIFT)
 
 /* Mesh of n_x x n_y x n_z rectangular cells of size dx x dy x dz (m). */
 typedef struct {
@@ -92,7 +113,8 @@ typedef struct demag_plan demag_plan;   /* opaque; owns N^ and the FFT workspace
  * FFT workspace.
  *   mesh    in   mesh description (copied).
  *   flags   in   DEMAG_FP32, DEMAG_BF16X2_MFMA or DEMAG_BF16X3_MFMA (one of them),
- *                optionally or-ed with DEMAG_EXTRAPOLATE_HD and DEMAG_POINT_DIPOLE.
+ *                optionally or-ed with DEMAG_EXTRAPOLATE_HD and DEMAG_POINT_DIPOLE;
+ *                with DEMAG_FP32 also DEMAG_PBC_X/Y/Z | DEMAG_PBC_IMAGES(P).
  *   stream  in   hipStream_t used for the set-up kernels; the call synchronises it.
  *   out     out  receives the new plan (NULL on failure).
  * Errors: EINVAL (null/invalid mesh), EUNSUPPORTED (size), ENOMEM, EHIP.

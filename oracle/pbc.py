@@ -112,23 +112,20 @@ class DemagPBC:
         return H
 
 
-def demag_pbc_direct(M, cell, pbc, images=DEFAULT_IMAGES, kind="newell"):
-    """The same field by the explicit double sum over cells and images (tiny
-    meshes only): H_i = -sum_j sum_m N(i - j + m L) M_j, with the components odd
-    in a periodic axis dropped at |r_d| = n_d/2 as in the kernel."""
-    M = np.asarray(M, dtype=np.float64)
-    _, nz, ny, nx = M.shape
-    n = (nx, ny, nz)
+def field_at(Mv, src, targets, n, cell, pbc, images=DEFAULT_IMAGES, kind="newell"):
+    """Explicit double sum over the given source cells and their images at the
+    given target cells: H_t = -sum_s sum_m N(t - s + m L) M_s, each periodic
+    displacement folded into (-n/2, n/2] and the components odd in a periodic
+    axis dropped at |r_d| = n_d/2 as in the kernel.  Mv (3, S) holds M at the
+    source cells src (S, 3) = (x, y, z); targets (T, 3).  Returns (3, T)."""
+    Mv = np.asarray(Mv, dtype=np.float64)
+    src = np.asarray(src)
     fn = _tensor_fn(kind)
     rng = [range(-images, images + 1) if p else range(0, 1) for p in pbc]
-    kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    src = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], 1)
-    Mflat = M.reshape(3, -1)
-    H = np.zeros_like(Mflat)
-    for t, (x, y, z) in enumerate(src):
-        d = np.array([x, y, z]) - src                      # (N, 3) displacements i - j
-        # fold each periodic displacement into (-n/2, n/2]
-        for axis in range(3):
+    H = np.zeros((3, len(targets)))
+    for t, tgt in enumerate(targets):
+        d = np.asarray(tgt)[None, :] - src                 # (S, 3) displacements t - s
+        for axis in range(3):                              # fold into (-n/2, n/2]
             if pbc[axis]:
                 v = n[axis]
                 d[:, axis] = np.where(d[:, axis] > v // 2, d[:, axis] - v, d[:, axis])
@@ -137,7 +134,7 @@ def demag_pbc_direct(M, cell, pbc, images=DEFAULT_IMAGES, kind="newell"):
         for mz in rng[2]:
             for my in rng[1]:
                 for mx in rng[0]:
-                    Nt += fn(d[:, 0] + mx * nx, d[:, 1] + my * ny, d[:, 2] + mz * nz, cell)
+                    Nt += fn(d[:, 0] + mx * n[0], d[:, 1] + my * n[1], d[:, 2] + mz * n[2], cell)
         for c, name in enumerate(newell.COMPONENTS):
             for axis in range(3):
                 v = n[axis]
@@ -145,5 +142,15 @@ def demag_pbc_direct(M, cell, pbc, images=DEFAULT_IMAGES, kind="newell"):
                     Nt[c, np.abs(d[:, axis]) == v // 2] = 0.0
         T = demag.tensor3(Nt)
         for a in range(3):
-            H[a, t] = -sum(np.dot(T[a][b], Mflat[b]) for b in range(3))
+            H[a, t] = -sum(np.dot(T[a][b], Mv[b]) for b in range(3))
+    return H
+
+
+def demag_pbc_direct(M, cell, pbc, images=DEFAULT_IMAGES, kind="newell"):
+    """The field of every cell by field_at over all cells (tiny meshes only)."""
+    M = np.asarray(M, dtype=np.float64)
+    _, nz, ny, nx = M.shape
+    kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    cells = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], 1)
+    H = field_at(M.reshape(3, -1), cells, cells, (nx, ny, nz), cell, pbc, images, kind)
     return H.reshape(M.shape)

@@ -26,6 +26,19 @@ DEMAG_BF16X2_MFMA = 1   # radix-16 passes as 2-term split BF16 MFMA products
 DEMAG_BF16X3_MFMA = 2   # 3-term split
 DEMAG_EXTRAPOLATE_HD = 8  # one H_d per RK4 step, quartic extrapolation at the sub-steps
 DEMAG_POINT_DIPOLE = 16   # point-dipole kernel of the lattice dipole-dipole field (Eq. 8)
+DEMAG_PBC_X = 32          # periodic axes (image-sum kernel, no padding; FP32 only)
+DEMAG_PBC_Y = 64
+DEMAG_PBC_Z = 128
+DEMAG_PBC_IMAGES_SHIFT = 8
+
+
+def pbc_flags(x=False, y=False, z=False, images=0):
+    """Plan flags for the periodic axes (x, y, z) with `images` (0..255) copies
+    summed on each side, or-ed into DEMAG_FP32."""
+    if not 0 <= int(images) <= 255:
+        raise ValueError("images must be in 0..255")
+    f = (DEMAG_PBC_X if x else 0) | (DEMAG_PBC_Y if y else 0) | (DEMAG_PBC_Z if z else 0)
+    return f | (int(images) << DEMAG_PBC_IMAGES_SHIFT) if f else 0
 
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EUNSUPPORTED", -4: "EHIP", -5: "EBUSY"}
 
@@ -312,7 +325,8 @@ def serve_close(server):
     return _check(load().serve_close(server))
 
 
-def kernel_shape(n):
-    """(6, Z1, X1, Y1) of the packed kernel for a mesh n = (nx, ny, nz)."""
-    d = [1 if v == 1 else v + 1 for v in n]
+def kernel_shape(n, pbc=(False, False, False)):
+    """(6, Z1, X1, Y1) of the packed kernel for a mesh n = (nx, ny, nz) with the
+    periodic axes pbc: D1 = N/2 + 1 with N = 2n (open) or n (periodic), 1 for N = 1."""
+    d = [1 if v == 1 else (v // 2 + 1 if p else v + 1) for v, p in zip(n, pbc)]
     return (6, d[2], d[0], d[1])

@@ -30,7 +30,7 @@ int fail(int code, const std::string& msg) {
 
 static bool pow2_or_one(int n) { return n >= 1 && (n & (n - 1)) == 0; }
 
-int make_geometry(int nx, int ny, int nz, Geometry* g) {
+int make_geometry(int nx, int ny, int nz, int pbc, int images, Geometry* g) {
     if (nx < 1 || ny < 1 || nz < 1) return fail(DEMAG_EINVAL, "mesh sizes must be >= 1");
     if (!pow2_or_one(nx) || !pow2_or_one(ny) || !pow2_or_one(nz))
         return fail(DEMAG_EUNSUPPORTED, "mesh sizes must be 1 or a power of two");
@@ -39,18 +39,32 @@ int make_geometry(int nx, int ny, int nz, Geometry* g) {
     g->nx = nx;
     g->ny = ny;
     g->nz = nz;
-    g->Nx = nx == 1 ? 1 : 2 * nx;
-    g->Ny = ny == 1 ? 1 : 2 * ny;
-    g->Nz = nz == 1 ? 1 : 2 * nz;
+    g->pbc = pbc & 7;
+    g->images = g->pbc ? images : 0;
+    // a periodic axis is transformed at its own length (circular convolution)
+    auto len = [](int n, bool per) { return (n == 1 || per) ? n : 2 * n; };
+    g->Nx = len(nx, g->px());
+    g->Ny = len(ny, g->py());
+    g->Nz = len(nz, g->pz());
     g->X1 = g->Nx == 1 ? 1 : g->Nx / 2 + 1;
     g->Y1 = g->Ny == 1 ? 1 : g->Ny / 2 + 1;
     g->Z1 = g->Nz == 1 ? 1 : g->Nz / 2 + 1;
+    g->Rx = g->px() ? nx / 2 + 1 : nx;
+    g->Ry = g->py() ? ny / 2 + 1 : ny;
+    g->Rz = g->pz() ? nz / 2 + 1 : nz;
     return DEMAG_OK;
 }
 
-int check_mesh(const demag_mesh* m, Geometry* g) {
+// Periodic axes and image count encoded in plan flags.
+static int flag_pbc(uint32_t flags) {
+    return ((flags & DEMAG_PBC_X) ? 1 : 0) | ((flags & DEMAG_PBC_Y) ? 2 : 0) |
+           ((flags & DEMAG_PBC_Z) ? 4 : 0);
+}
+static int flag_images(uint32_t flags) { return (int)((flags >> DEMAG_PBC_IMAGES_SHIFT) & 0xffu); }
+
+int check_mesh(const demag_mesh* m, Geometry* g, uint32_t flags) {
     if (!m) return fail(DEMAG_EINVAL, "mesh is NULL");
-    int rc = make_geometry(m->nx, m->ny, m->nz, g);
+    int rc = make_geometry(m->nx, m->ny, m->nz, flag_pbc(flags), flag_images(flags), g);
     if (rc) return rc;
     const double h[3] = {m->dx, m->dy, m->dz};
     for (double v : h)
@@ -75,7 +89,7 @@ Spectrum::~Spectrum() {
     if (K) (void)hipFree(K);
 }
 
-using SpecKey = std::tuple<int, int, int, int, double, double, double, int>;
+using SpecKey = std::tuple<int, int, int, int, double, double, double, int, int, int>;
 static std::mutex g_spec_mu;
 static std::map<SpecKey, std::weak_ptr<Spectrum>> g_spec;
 
@@ -83,7 +97,7 @@ int get_spectrum(const Geometry& g, double dx, double dy, double dz, int kind, h
                  std::shared_ptr<Spectrum>* out) {
     int dev = 0;
     (void)hipGetDevice(&dev);
-    SpecKey key{dev, g.nx, g.ny, g.nz, dx, dy, dz, kind};
+    SpecKey key{dev, g.nx, g.ny, g.nz, dx, dy, dz, kind, g.pbc, g.images};
     std::lock_guard<std::mutex> lk(g_spec_mu);
     auto it = g_spec.find(key);
     if (it != g_spec.end()) {
@@ -149,7 +163,7 @@ int s2_planes(const Geometry& g) {
 }
 
 bool uses_xz(const Geometry& g, uint32_t flags) {
-    return (flags & 3) == DEMAG_FP32 && xz_supported(g.nx, g.ny, g.nz);
+    return (flags & 3) == DEMAG_FP32 && g.pbc == 0 && xz_supported(g.nx, g.ny, g.nz);
 }
 
 size_t workspace_bytes(const Geometry& g, uint32_t flags) {
@@ -193,7 +207,7 @@ void free_plan(demag_plan* p) {
 int create_plan(const demag_mesh* mesh, uint32_t flags, hipStream_t s, demag_plan** out) {
     *out = nullptr;
     Geometry g;
-    int rc = check_mesh(mesh, &g);
+    int rc = check_mesh(mesh, &g, flags);
     if (rc) return rc;
     demag_plan* p = new (std::nothrow) demag_plan();
     if (!p) return fail(DEMAG_ENOMEM, "host allocation failed");
@@ -231,7 +245,7 @@ int create_plan(const demag_mesh* mesh, uint32_t flags, hipStream_t s, demag_pla
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find({g.nx, g.ny, g.nz, p->mf});
-        if (it != g_tuned.end() && !p->xz) {
+        if (it != g_tuned.end() && !p->xz && g.pbc == 0) {
             for (int i = 0; i < 5; ++i) p->variant[i] = it->second.variant[i];
             p->nch = it->second.nch;
         }
@@ -305,31 +319,31 @@ static int run_field_single(demag_plan* p, const float* M, float* H, float scale
     }
     {
         StageTimer t(p, DEMAG_STAGE_X_FWD, s);
-        if ((rc = launch_x_forward(one(xdesc(p, M, H, scale)), g.nx, p->variant[0], p->mf, p->tw, s))) return rc;
+        if ((rc = launch_x_forward(one(xdesc(p, M, H, scale)), g.nx, p->variant[0], p->mf, p->tw, s, g.px()))) return rc;
     }
     if (g.ny == 1) {
         StageTimer t(p, DEMAG_STAGE_Z_CONV, s);
-        if ((rc = launch_z_convolve(one(zdesc(p, 0, g.X1)), g.Nz, p->variant[2], p->mf, p->tw, s))) return rc;
+        if ((rc = launch_z_convolve(one(zdesc(p, 0, g.X1)), g.Nz, p->variant[2], p->mf, p->tw, s, g.pz()))) return rc;
     } else {
         const int per = (g.X1 + p->nch - 1) / p->nch;
         for (int k0 = 0; k0 < g.X1; k0 += per) {
             const int nk = per < g.X1 - k0 ? per : g.X1 - k0;
             {
                 StageTimer t(p, DEMAG_STAGE_Y_FWD, s);
-                if ((rc = launch_y_forward(one(ydesc(p, k0, nk)), g.ny, p->variant[1], p->mf, p->tw, s))) return rc;
+                if ((rc = launch_y_forward(one(ydesc(p, k0, nk)), g.ny, p->variant[1], p->mf, p->tw, s, g.py()))) return rc;
             }
             {
                 StageTimer t(p, DEMAG_STAGE_Z_CONV, s);
-                if ((rc = launch_z_convolve(one(zdesc(p, k0, nk)), g.Nz, p->variant[2], p->mf, p->tw, s))) return rc;
+                if ((rc = launch_z_convolve(one(zdesc(p, k0, nk)), g.Nz, p->variant[2], p->mf, p->tw, s, g.pz()))) return rc;
             }
             {
                 StageTimer t(p, DEMAG_STAGE_Y_INV, s);
-                if ((rc = launch_y_inverse(one(ydesc(p, k0, nk)), g.ny, p->variant[3], p->mf, p->tw, s))) return rc;
+                if ((rc = launch_y_inverse(one(ydesc(p, k0, nk)), g.ny, p->variant[3], p->mf, p->tw, s, g.py()))) return rc;
             }
         }
     }
     StageTimer t(p, DEMAG_STAGE_X_INV, s);
-    return launch_x_inverse(one(xdesc(p, M, H, scale)), g.nx, p->variant[4], p->mf, p->tw, s);
+    return launch_x_inverse(one(xdesc(p, M, H, scale)), g.nx, p->variant[4], p->mf, p->tw, s, g.px());
 }
 
 // Groups item indices by a key, keeping first-appearance order, in runs of at most MAXB.
@@ -390,41 +404,53 @@ int run_fields(demag_plan* const* plans, const float* const* M, float* const* H,
     }
     if (items.empty()) return DEMAG_OK;
     const float2* tw = plans[items[0]]->tw;
-    auto by_nx = groups(items, [&](int i) { return plans[i]->g.nx * 8LL + plans[i]->mf; });
+    // a shared launch needs one transform length, MFMA form and periodicity
+    auto by_nx = groups(items, [&](int i) {
+        return (plans[i]->g.nx * 8LL + plans[i]->mf) * 2 + plans[i]->g.px();
+    });
     std::vector<int> yitems;
     for (int i : items)
         if (plans[i]->g.ny > 1) yitems.push_back(i);
-    auto by_ny = groups(yitems, [&](int i) { return plans[i]->g.ny * 8LL + plans[i]->mf; });
-    auto by_nz = groups(items, [&](int i) { return plans[i]->g.Nz * 8LL + plans[i]->mf; });
+    auto by_ny = groups(yitems, [&](int i) {
+        return (plans[i]->g.ny * 8LL + plans[i]->mf) * 2 + plans[i]->g.py();
+    });
+    auto by_nz = groups(items, [&](int i) {
+        return (plans[i]->g.Nz * 8LL + plans[i]->mf) * 2 + plans[i]->g.pz();
+    });
     for (auto& grp : by_nx) {
         XBatch b;
         b.count = (int)grp.size();
         for (int r = 0; r < b.count; ++r) b.d[r] = xdesc(plans[grp[r]], M[grp[r]], H[grp[r]], scale[grp[r]]);
-        if ((rc = launch_x_forward(b, plans[grp[0]]->g.nx, plans[grp[0]]->variant[0], plans[grp[0]]->mf, tw, s))) return rc;
+        if ((rc = launch_x_forward(b, plans[grp[0]]->g.nx, plans[grp[0]]->variant[0], plans[grp[0]]->mf, tw, s,
+                                   plans[grp[0]]->g.px()))) return rc;
     }
     for (auto& grp : by_ny) {
         YBatch b;
         b.count = (int)grp.size();
         for (int r = 0; r < b.count; ++r) b.d[r] = ydesc(plans[grp[r]], 0, plans[grp[r]]->g.X1);
-        if ((rc = launch_y_forward(b, plans[grp[0]]->g.ny, plans[grp[0]]->variant[1], plans[grp[0]]->mf, tw, s))) return rc;
+        if ((rc = launch_y_forward(b, plans[grp[0]]->g.ny, plans[grp[0]]->variant[1], plans[grp[0]]->mf, tw, s,
+                                   plans[grp[0]]->g.py()))) return rc;
     }
     for (auto& grp : by_nz) {
         ZBatch b;
         b.count = (int)grp.size();
         for (int r = 0; r < b.count; ++r) b.d[r] = zdesc(plans[grp[r]], 0, plans[grp[r]]->g.X1);
-        if ((rc = launch_z_convolve(b, plans[grp[0]]->g.Nz, plans[grp[0]]->variant[2], plans[grp[0]]->mf, tw, s))) return rc;
+        if ((rc = launch_z_convolve(b, plans[grp[0]]->g.Nz, plans[grp[0]]->variant[2], plans[grp[0]]->mf, tw, s,
+                                    plans[grp[0]]->g.pz()))) return rc;
     }
     for (auto& grp : by_ny) {
         YBatch b;
         b.count = (int)grp.size();
         for (int r = 0; r < b.count; ++r) b.d[r] = ydesc(plans[grp[r]], 0, plans[grp[r]]->g.X1);
-        if ((rc = launch_y_inverse(b, plans[grp[0]]->g.ny, plans[grp[0]]->variant[3], plans[grp[0]]->mf, tw, s))) return rc;
+        if ((rc = launch_y_inverse(b, plans[grp[0]]->g.ny, plans[grp[0]]->variant[3], plans[grp[0]]->mf, tw, s,
+                                   plans[grp[0]]->g.py()))) return rc;
     }
     for (auto& grp : by_nx) {
         XBatch b;
         b.count = (int)grp.size();
         for (int r = 0; r < b.count; ++r) b.d[r] = xdesc(plans[grp[r]], M[grp[r]], H[grp[r]], scale[grp[r]]);
-        if ((rc = launch_x_inverse(b, plans[grp[0]]->g.nx, plans[grp[0]]->variant[4], plans[grp[0]]->mf, tw, s))) return rc;
+        if ((rc = launch_x_inverse(b, plans[grp[0]]->g.nx, plans[grp[0]]->variant[4], plans[grp[0]]->mf, tw, s,
+                                   plans[grp[0]]->g.px()))) return rc;
     }
     return DEMAG_OK;
 }
@@ -447,6 +473,7 @@ static LLGDesc llg_desc(const LLGStep& st, const float* ms, float* out, const fl
     d.cx = g.nx > 1 ? (float)(cex / (p->dx * p->dx)) : 0.f;
     d.cy = g.ny > 1 ? (float)(cex / (p->dy * p->dy)) : 0.f;
     d.cz = g.nz > 1 ? (float)(cex / (p->dz * p->dz)) : 0.f;
+    d.pbc = g.pbc;
     for (int k = 0; k < 3; ++k) d.hz[k] = (float)st.prm.Hzee[k];
     d.gam = (float)(st.prm.gamma / (1.0 + st.prm.alpha * st.prm.alpha));
     d.alpha = (float)st.prm.alpha;
@@ -585,8 +612,12 @@ struct atom_plan {
 };
 
 static bool valid_flags(uint32_t flags) {
-    const uint32_t prec = flags & ~(uint32_t)(DEMAG_EXTRAPOLATE_HD | DEMAG_POINT_DIPOLE);
-    return prec == DEMAG_FP32 || prec == DEMAG_BF16X2_MFMA || prec == DEMAG_BF16X3_MFMA;
+    const uint32_t pbc = DEMAG_PBC_X | DEMAG_PBC_Y | DEMAG_PBC_Z;
+    const uint32_t prec = flags & ~(uint32_t)(DEMAG_EXTRAPOLATE_HD | DEMAG_POINT_DIPOLE | pbc |
+                                              (0xffu << DEMAG_PBC_IMAGES_SHIFT));
+    if (prec != DEMAG_FP32 && prec != DEMAG_BF16X2_MFMA && prec != DEMAG_BF16X3_MFMA) return false;
+    if ((flags & pbc) == 0) return (flags >> DEMAG_PBC_IMAGES_SHIFT) == 0;  // images need an axis
+    return prec == DEMAG_FP32;  // the periodic stages exist in FP32 only
 }
 
 extern "C" {
@@ -596,7 +627,7 @@ const char* demag_last_error(void) { return g_last_error.c_str(); }
 size_t demag_plan_bytes(const demag_mesh* mesh, uint32_t flags) {
     Geometry g;
     if (!valid_flags(flags)) return 0;
-    if (check_mesh(mesh, &g) != DEMAG_OK) return 0;
+    if (check_mesh(mesh, &g, flags) != DEMAG_OK) return 0;
     return g.k_elems() * sizeof(float) + workspace_bytes(g, flags);
 }
 
@@ -607,6 +638,9 @@ int demag_setup(const demag_mesh* mesh, uint32_t flags, void* stream, demag_plan
         Geometry g;
         int rc = check_mesh(mesh, &g);
         if (rc) return rc;
+        const bool pbc = flags & (DEMAG_PBC_X | DEMAG_PBC_Y | DEMAG_PBC_Z);
+        if (pbc && valid_flags(flags & ~(uint32_t)3))
+            return fail(DEMAG_EUNSUPPORTED, "periodic boundary conditions need DEMAG_FP32");
         return fail(DEMAG_EUNSUPPORTED, "unknown flags");
     }
     int rc = create_plan(mesh, flags, (hipStream_t)stream, out);
@@ -731,7 +765,7 @@ int demag_autotune(demag_plan* plan, void* stream) {
     //    in one tile shape only)
     rc = run_field_single(plan, M, H, 1.0f, s);
     const int per = (g.X1 + plan->nch - 1) / plan->nch;
-    for (int st = 0; st < 5 && !rc && plan->mf == 0 && !plan->xz; ++st) {
+    for (int st = 0; st < 5 && !rc && plan->mf == 0 && !plan->xz && g.pbc == 0; ++st) {
         if ((st == 1 || st == 3) && g.ny == 1) continue;
         double best = 1e30;
         int best_v = plan->variant[st];
@@ -774,6 +808,7 @@ int demag_autotune(demag_plan* plan, void* stream) {
     plan->timing_cap = saved_cap;
     cleanup();
     if (rc) return rc;
+    if (g.pbc) return DEMAG_OK;  // periodic plans share no tuning with open ones
     std::lock_guard<std::mutex> lk(g_tune_mu);
     Tuned t;
     for (int i = 0; i < 5; ++i) t.variant[i] = plan->variant[i];
@@ -840,6 +875,8 @@ int atom_setup(const atom_mesh* mesh, uint32_t flags, void* stream, atom_plan** 
     if (mesh->nx % mesh->macro || mesh->ny % mesh->macro || mesh->nz % mesh->macro)
         return fail(DEMAG_EINVAL, "macro must divide every lattice size");
     if (!(mesh->a > 0.0) || !std::isfinite(mesh->a)) return fail(DEMAG_EINVAL, "a must be > 0");
+    if (flags & (DEMAG_PBC_X | DEMAG_PBC_Y | DEMAG_PBC_Z))
+        return fail(DEMAG_EUNSUPPORTED, "atomistic plans take open boundaries only");
     demag_mesh dm_mesh;
     dm_mesh.nx = mesh->nx / mesh->macro;
     dm_mesh.ny = mesh->ny / mesh->macro;

@@ -60,18 +60,20 @@ __global__ __launch_bounds__(256) void llg_stage_kernel(const LLGBatch b, int st
     const float* __restrict__ ms = a.ms;
     const int x = (int)(p % a.nx), y = (int)(p / a.nx), z = zt;
     float3 c = load3(ms, i, N);
-    // free boundaries: a missing neighbour is replaced by the cell itself
+    // free boundaries: a missing neighbour is replaced by the cell itself; along
+    // a periodic axis the first and last cells are neighbours
     float3 lap = make_float3(0.f, 0.f, 0.f);
-    auto add_axis = [&](float coef, bool has_lo, bool has_hi, size_t stride) {
-        float3 l = has_lo ? load3(ms, i - stride, N) : c;
-        float3 r = has_hi ? load3(ms, i + stride, N) : c;
+    auto add_axis = [&](float coef, int pos, int n, size_t stride, bool per) {
+        const size_t wrap = (size_t)(n - 1) * stride;
+        float3 l = pos > 0 ? load3(ms, i - stride, N) : (per ? load3(ms, i + wrap, N) : c);
+        float3 r = pos < n - 1 ? load3(ms, i + stride, N) : (per ? load3(ms, i - wrap, N) : c);
         lap.x = fmaf(coef, (l.x + r.x) - 2.f * c.x, lap.x);
         lap.y = fmaf(coef, (l.y + r.y) - 2.f * c.y, lap.y);
         lap.z = fmaf(coef, (l.z + r.z) - 2.f * c.z, lap.z);
     };
-    if (a.nx > 1) add_axis(a.cx, x > 0, x < a.nx - 1, 1);
-    if (a.ny > 1) add_axis(a.cy, y > 0, y < a.ny - 1, (size_t)a.nx);
-    if (a.nz > 1) add_axis(a.cz, z > 0, z < a.nz - 1, (size_t)a.nx * a.ny);
+    if (a.nx > 1) add_axis(a.cx, x, a.nx, 1, a.pbc & 1);
+    if (a.ny > 1) add_axis(a.cy, y, a.ny, (size_t)a.nx, a.pbc & 2);
+    if (a.nz > 1) add_axis(a.cz, z, a.nz, (size_t)a.nx * a.ny, a.pbc & 4);
     float3 hd = load3(a.Hd, i, N);
     float3 H = make_float3(hd.x + lap.x + a.hz[0], hd.y + lap.y + a.hz[1], hd.z + lap.z + a.hz[2]);
     float3 k = ll_rhs(c, H, a.gam, a.alpha);

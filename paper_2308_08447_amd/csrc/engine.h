@@ -37,8 +37,14 @@ __device__ __forceinline__ int xcd_tile(int b, int B) {
 
 struct Geometry {
     int nx, ny, nz;        // cells
-    int Nx, Ny, Nz;        // padded transform lengths (2n, or 1 when n = 1)
+    int Nx, Ny, Nz;        // transform lengths: 2n (open axis), n (periodic), 1 when n = 1
     int X1, Y1, Z1;        // distinct folded frequencies: N/2 + 1, or 1
+    int pbc = 0;           // periodic axes: bit 0 x, bit 1 y, bit 2 z
+    int images = 0;        // periodic images summed on each side of a periodic axis
+    int Rx, Ry, Rz;        // tensor octant extents: n (open), n/2 + 1 (periodic)
+    bool px() const { return pbc & 1; }
+    bool py() const { return (pbc >> 1) & 1; }
+    bool pz() const { return (pbc >> 2) & 1; }
     size_t cells() const { return (size_t)nx * ny * nz; }
     size_t s1_elems() const { return (size_t)3 * nz * X1 * ny; }   // complex
     size_t s2_elems() const { return (size_t)3 * nz * X1 * Ny; }   // complex
@@ -46,9 +52,13 @@ struct Geometry {
 };
 
 // Returns DEMAG_OK or an error code (and message) for a mesh the kernels cannot take.
-int make_geometry(int nx, int ny, int nz, Geometry* g);
+// pbc: periodic axes (bit 0 x, 1 y, 2 z); images: copies summed on each side.
+int make_geometry(int nx, int ny, int nz, int pbc, int images, Geometry* g);
 
-// ---- FFT stage launchers (stages.hip) -----------------------------------------
+// ---- FFT stage launchers (stages_*.hip) ---------------------------------------
+// periodic = true: the axis of the stage is periodic, its transform has the
+// mesh length n (no zero padding) and every output is kept; FP32 and the
+// middle tile variant only.
 // A launch processes a batch of up to MAXB independent work items (one mesh
 // each) that share the stage's transform length; the descriptors travel in the
 // kernel arguments, so launches need no device-side tables and can be captured
@@ -98,11 +108,16 @@ using XBatch = StageBatch<XDesc>;
 using YBatch = StageBatch<YDesc>;
 using ZBatch = StageBatch<ZDesc>;
 
-int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hipStream_t s);
-int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hipStream_t s);
-int launch_y_forward(YBatch b, int ny, int variant, int mf, const float2* tw, hipStream_t s);
-int launch_y_inverse(YBatch b, int ny, int variant, int mf, const float2* tw, hipStream_t s);
-int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, hipStream_t s);
+int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hipStream_t s,
+                     bool periodic = false);
+int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hipStream_t s,
+                     bool periodic = false);
+int launch_y_forward(YBatch b, int ny, int variant, int mf, const float2* tw, hipStream_t s,
+                     bool periodic = false);
+int launch_y_inverse(YBatch b, int ny, int variant, int mf, const float2* tw, hipStream_t s,
+                     bool periodic = false);
+int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, hipStream_t s,
+                      bool periodic = false);
 bool xz_supported(int nx, int ny, int nz);
 size_t xz_t_elems(int nx, int ny, int nz);
 int xz_groups(int X1);  // kx groups of T
@@ -128,6 +143,7 @@ struct LLGDesc {           // one mesh in a batched RK4 stage update
     float* out;            // next stage input (may alias m in the last stage)
     int nx, ny, nz;
     float cx, cy, cz;      // 2A/(mu0 Ms h_d^2), 0 for an axis with one cell
+    int pbc;               // periodic axes (bit 0 x, 1 y, 2 z): neighbours wrap around
     float hz[3];
     float gam;             // gamma/(1+alpha^2)
     float alpha;

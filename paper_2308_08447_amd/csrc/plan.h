@@ -37,7 +37,8 @@ size_t rk_bytes(const Geometry& g);
 int s2_planes(const Geometry& g);
 
 int dev_alloc(void** p, size_t bytes, const char* what);
-int check_mesh(const demag_mesh* m, Geometry* g);
+// flags: plan flags (periodic axes and image count); 0 for an open mesh
+int check_mesh(const demag_mesh* m, Geometry* g, uint32_t flags = 0);
 int check_llg_params(const llg_params* prm, double dt, int32_t nsteps);
 
 }  // namespace dm

@@ -9,9 +9,12 @@ namespace dm {
 // odd outputs: DFT of z W_2L^t); the first pass reads the rows straight from M,
 // the last pass leaves the spectrum in LDS in natural order, from where the
 // Hermitian separation writes S1 transposed (consecutive threads, consecutive y).
-template <int L, int TY, int MF>
+// PX (periodic x, transform length L): the DFT of z alone gives the L/2 + 1
+// frequencies, stored at kx = m.
+template <int L, int TY, int MF, bool PX = false>
 __global__ __launch_bounds__(NT) void x_forward_kernel(const XBatch b,
                                                        const float2* __restrict__ tw_all) {
+    constexpr int X1 = PX ? L / 2 + 1 : L + 1;
     constexpr int NP = TY / 2;
     constexpr int LS = lpad_c(L) + 1;  // odd stride: the pairs of one frequency hit distinct banks
     __shared__ float2 buf[NP * LS];
@@ -30,7 +33,7 @@ __global__ __launch_bounds__(NT) void x_forward_kernel(const XBatch b,
     const int y0 = (id % nyt) * TY, z = (id / nyt) % nz, c = id / (nyt * nz);
     const int rows = min(TY, ny - y0);
     const float* src = M + ((size_t)(c * nz + z) * ny + y0) * L;
-    float2* dst = S1 + (size_t)(c * nz + z) * (L + 1) * ny + y0;
+    float2* dst = S1 + (size_t)(c * nz + z) * X1 * ny + y0;
 
     auto pair = [&](int p, int t) {
         float a = (2 * p < rows) ? src[(size_t)(2 * p) * L + t] : 0.f;
@@ -51,8 +54,9 @@ __global__ __launch_bounds__(NT) void x_forward_kernel(const XBatch b,
         float2 Xa = cscale(cadd(Zk, Zn), 0.5f);
         float2 d = csub(Zk, Zn);
         float2 Xb = make_float2(0.5f * d.y, -0.5f * d.x);
-        store_pair(dst + (size_t)(2 * m) * ny + 2 * p, Xa, Xb, rows - 2 * p);
+        store_pair(dst + (size_t)(PX ? m : 2 * m) * ny + 2 * p, Xa, Xb, rows - 2 * p);
     }
+    if constexpr (PX) return;
     __syncthreads();
     fft_io<L, -1, NP, NT, Rows, false, false, true, MF>(buf, twL, pair_odd, to_lds);
     __syncthreads();
@@ -72,17 +76,19 @@ __global__ __launch_bounds__(NT) void x_forward_kernel(const XBatch b,
 // from S1 (consecutive threads, consecutive y) into LDS; the inverse of the even
 // part is parked in a second LDS region, and the last pass of the odd part
 // combines z[t] = IE[t] + W_2L^-t IO[t] and stores both rows of H directly.
-template <int L, int TY, int MF>
+// PX (periodic x): the L inputs Z[m] come from kx = m and their inverse is z.
+template <int L, int TY, int MF, bool PX = false>
 __global__ __launch_bounds__(NT) void x_inverse_kernel(const XBatch b,
                                                        const float2* __restrict__ tw_all) {
+    constexpr int X1 = PX ? L / 2 + 1 : L + 1;
     constexpr int NP = TY / 2;
     constexpr int LS = lpad_c(L) + 1;  // odd stride: the pairs of one frequency hit distinct banks
     __shared__ float2 buf[NP * LS];
-    __shared__ float2 ie[NP * LS];
+    __shared__ float2 ie[PX ? 1 : NP * LS];
     __shared__ float2 twL[L];
-    __shared__ float2 tw2L[L];  // first half of the length-2L table
+    __shared__ float2 tw2L[PX ? 1 : L];  // first half of the length-2L table
     stage_table(twL, tw_all + L, L);
-    stage_table(tw2L, tw_all + 2 * L, L);
+    if constexpr (!PX) stage_table(tw2L, tw_all + 2 * L, L);
     const int tid = threadIdx.x;
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
@@ -93,25 +99,33 @@ __global__ __launch_bounds__(NT) void x_inverse_kernel(const XBatch b,
     const int id = gid - b.start[item];
     const int y0 = (id % nyt) * TY, z = (id / nyt) % nz, c = id / (nyt * nz);
     const int rows = min(TY, ny - y0);
-    const float2* src = S1 + (size_t)(c * nz + z) * (L + 1) * ny + y0;
+    const float2* src = S1 + (size_t)(c * nz + z) * X1 * ny + y0;
     float* dst = H + ((size_t)(c * nz + z) * ny + y0) * L;
     using Rows = RowLines<LS>;
 
     // Z[k] = Xa[k] + i Xb[k]; for k > L use Hermitian symmetry X[2L-k] = conj(X[k]).
     // The DC and Nyquist bins of a real row are real: their imaginary parts are dropped.
     for (int it = tid; it < (L / 2 + 1) * NP; it += NT) {
-        int p = it % NP, m = it / NP, kx = 2 * m;
+        int p = it % NP, m = it / NP, kx = PX ? m : 2 * m;
         float2 Xa, Xb;
         load_pair(src + (size_t)kx * ny + 2 * p, Xa, Xb, rows - 2 * p);
-        if (kx == 0 || kx == L) {
+        if (m == 0 || 2 * m == L) {
             Xa.y = 0.f;
             Xb.y = 0.f;
         }
         buf[p * LS + lpad(m)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
-        if (kx > 0 && kx < L) buf[p * LS + lpad(L - m)] = make_float2(Xa.x + Xb.y, Xb.x - Xa.y);
+        if (m > 0 && 2 * m < L) buf[p * LS + lpad(L - m)] = make_float2(Xa.x + Xb.y, Xb.x - Xa.y);
     }
     __syncthreads();
     auto from_lds = [&](int p, int t) { return buf[p * LS + lpad(t)]; };
+    if constexpr (PX) {
+        auto rows_out = [&](int p, int t, float2 zz) {
+            if (2 * p < rows) dst[(size_t)(2 * p) * L + t] = zz.x;
+            if (2 * p + 1 < rows) dst[(size_t)(2 * p + 1) * L + t] = zz.y;
+        };
+        fft_io<L, +1, NP, NT, Rows, false, false, true, MF>(buf, twL, from_lds, rows_out);
+        return;
+    }
     auto park = [&](int p, int t, float2 v) { ie[p * LS + lpad(t)] = v; };
     fft_io<L, +1, NP, NT, Rows, false, false, true, MF>(buf, twL, from_lds, park);
     __syncthreads();
@@ -145,13 +159,35 @@ __global__ void x_copy_inverse_kernel(const float2* __restrict__ S1, float* __re
 }
 
 
-int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hipStream_t s) {
+int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hipStream_t s,
+                     bool periodic) {
     if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "x stage: bad batch size");
     if (nx == 1) {
         for (int r = 0; r < b.count; ++r) {
             size_t n = (size_t)3 * b.d[r].nz * b.d[r].ny;
             hipLaunchKernelGGL(x_copy_forward_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                                s, b.d[r].M, b.d[r].S1, n, b.d[r].scale);
+        }
+        DM_CHECK_LAUNCH();
+        return DEMAG_OK;
+    }
+    if (periodic) {
+        if (mf) return fail(DEMAG_EUNSUPPORTED, "x stage: periodic transforms are FP32 only");
+        switch (nx) {
+#define CASE(Lv)                                                                                  \
+    case Lv: {                                                                                    \
+        constexpr int L = Lv;                                                                     \
+        constexpr int TY = XTile<L, 1, false>::TY;                                                  \
+        b.start[0] = 0;                                                                           \
+        for (int r = 0; r < b.count; ++r)                                                         \
+            b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;           \
+        hipLaunchKernelGGL((x_forward_kernel<L, TY, 0, true>), dim3((unsigned)finish_batch(b)),       \
+                           dim3(NT), 0, s, b, tw);                                                \
+        break;                                                                                    \
+    }
+            DM_POW2_CASES(CASE)
+#undef CASE
+            default: return fail(DEMAG_EUNSUPPORTED, "x stage: unsupported nx");
         }
         DM_CHECK_LAUNCH();
         return DEMAG_OK;
@@ -181,13 +217,35 @@ int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hi
     return DEMAG_OK;
 }
 
-int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hipStream_t s) {
+int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hipStream_t s,
+                     bool periodic) {
     if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "x stage: bad batch size");
     if (nx == 1) {
         for (int r = 0; r < b.count; ++r) {
             size_t n = (size_t)3 * b.d[r].nz * b.d[r].ny;
             hipLaunchKernelGGL(x_copy_inverse_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                                s, b.d[r].S1, b.d[r].H, n);
+        }
+        DM_CHECK_LAUNCH();
+        return DEMAG_OK;
+    }
+    if (periodic) {
+        if (mf) return fail(DEMAG_EUNSUPPORTED, "x stage: periodic transforms are FP32 only");
+        switch (nx) {
+#define CASE(Lv)                                                                                  \
+    case Lv: {                                                                                    \
+        constexpr int L = Lv;                                                                     \
+        constexpr int TY = XTile<L, 1, true>::TY;                                                  \
+        b.start[0] = 0;                                                                           \
+        for (int r = 0; r < b.count; ++r)                                                         \
+            b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;           \
+        hipLaunchKernelGGL((x_inverse_kernel<L, TY, 0, true>), dim3((unsigned)finish_batch(b)),       \
+                           dim3(NT), 0, s, b, tw);                                                \
+        break;                                                                                    \
+    }
+            DM_POW2_CASES(CASE)
+#undef CASE
+            default: return fail(DEMAG_EUNSUPPORTED, "x stage: unsupported nx");
         }
         DM_CHECK_LAUNCH();
         return DEMAG_OK;

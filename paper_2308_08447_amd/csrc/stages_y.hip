@@ -9,11 +9,12 @@ namespace dm {
 // One block: LPB lines (consecutive kx) of one (c, z) plane.  Each line is a
 // length-Ny = 2L transform whose upper L inputs are zero (forward) or whose
 // upper L outputs are dropped (inverse); the first pass reads S1/S2 straight
-// into registers and the last pass stores straight from registers.
-template <int L, int LPB, int MF>
+// into registers and the last pass stores straight from registers.  PY
+// (periodic y): a plain length-L transform, Ny = L.
+template <int L, int LPB, int MF, bool PY = false>
 __global__ __launch_bounds__(NT) void y_forward_kernel(const YBatch b,
                                                        const float2* __restrict__ tw_all) {
-    constexpr int LN = 2 * L;
+    constexpr int LN = PY ? L : 2 * L;
     constexpr int LS = lpad_c(LN);
     __shared__ float2 buf[LPB * LS];
     __shared__ float2 tw[LN];
@@ -34,13 +35,13 @@ __global__ __launch_bounds__(NT) void y_forward_kernel(const YBatch b,
     auto sink = [&](int l, int k, float2 v) {
         if (l < nl) out[(size_t)l * LN + k] = v;
     };
-    fft_io<LN, -1, LPB, NT, RowLines<LS>, true, false, false, MF>(buf, tw, src, sink);
+    fft_io<LN, -1, LPB, NT, RowLines<LS>, !PY, false, false, MF>(buf, tw, src, sink);
 }
 
-template <int L, int LPB, int MF>
+template <int L, int LPB, int MF, bool PY = false>
 __global__ __launch_bounds__(NT) void y_inverse_kernel(const YBatch b,
                                                        const float2* __restrict__ tw_all) {
-    constexpr int LN = 2 * L;
+    constexpr int LN = PY ? L : 2 * L;
     constexpr int LS = lpad_c(LN);
     __shared__ float2 buf[LPB * LS];
     __shared__ float2 tw[LN];
@@ -61,14 +62,40 @@ __global__ __launch_bounds__(NT) void y_inverse_kernel(const YBatch b,
     auto sink = [&](int l, int k, float2 v) {
         if (l < nl) out[(size_t)l * L + k] = v;
     };
-    fft_io<LN, +1, LPB, NT, RowLines<LS>, false, true, false, MF>(buf, tw, src, sink);
+    fft_io<LN, +1, LPB, NT, RowLines<LS>, false, !PY, false, MF>(buf, tw, src, sink);
 }
 
 
 template <bool INVERSE>
-static int launch_y(YBatch b, int ny, int variant, int mf, const float2* tw, hipStream_t s) {
+static int launch_y(YBatch b, int ny, int variant, int mf, const float2* tw, hipStream_t s,
+                    bool periodic) {
     if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "y stage: bad batch size");
     if (ny == 1) return DEMAG_OK;  // no y transform (S2 aliases S1)
+    if (periodic) {
+        if (mf) return fail(DEMAG_EUNSUPPORTED, "y stage: periodic transforms are FP32 only");
+        switch (ny) {
+#define CASE(Lv)                                                                              \
+    case Lv: {                                                                                \
+        constexpr int L = Lv;                                                                 \
+        constexpr int LPB = L >= 2048 ? 1 : 2048 / L;                                         \
+        b.start[0] = 0;                                                                       \
+        for (int r = 0; r < b.count; ++r)                                                     \
+            b.start[r + 1] = b.start[r] + ((b.d[r].nk + LPB - 1) / LPB) * b.d[r].nz * 3;     \
+        if (INVERSE)                                                                          \
+            hipLaunchKernelGGL((y_inverse_kernel<L, LPB, 0, true>),                           \
+                               dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);       \
+        else                                                                                  \
+            hipLaunchKernelGGL((y_forward_kernel<L, LPB, 0, true>),                           \
+                               dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);       \
+        break;                                                                                \
+    }
+            DM_POW2_CASES(CASE)
+#undef CASE
+            default: return fail(DEMAG_EUNSUPPORTED, "y stage: unsupported ny");
+        }
+        DM_CHECK_LAUNCH();
+        return DEMAG_OK;
+    }
     switch (ny) {
 #define BODY(V)                                                                                 \
     {                                                                                           \
@@ -98,11 +125,13 @@ static int launch_y(YBatch b, int ny, int variant, int mf, const float2* tw, hip
     return DEMAG_OK;
 }
 
-int launch_y_forward(YBatch b, int ny, int variant, int mf, const float2* tw, hipStream_t s) {
-    return launch_y<false>(b, ny, variant, mf, tw, s);
+int launch_y_forward(YBatch b, int ny, int variant, int mf, const float2* tw, hipStream_t s,
+                     bool periodic) {
+    return launch_y<false>(b, ny, variant, mf, tw, s, periodic);
 }
-int launch_y_inverse(YBatch b, int ny, int variant, int mf, const float2* tw, hipStream_t s) {
-    return launch_y<true>(b, ny, variant, mf, tw, s);
+int launch_y_inverse(YBatch b, int ny, int variant, int mf, const float2* tw, hipStream_t s,
+                     bool periodic) {
+    return launch_y<true>(b, ny, variant, mf, tw, s, periodic);
 }
 
 

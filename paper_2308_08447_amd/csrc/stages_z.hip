@@ -12,10 +12,11 @@ namespace dm {
 // loaded into registers together with the K tile (so every global load of the
 // block is in flight at once), then staged in LDS: element (z, c, column) at
 // z * 3NC + c * NC + column, i.e. 3NC interleaved lines of length NZ.
-template <int NZ, int TH, int MF>
+// PZ (periodic z): NZ = nz, every z plane is stored and every output kept.
+template <int NZ, int TH, int MF, bool PZ = false>
 __global__ __launch_bounds__(NT) void z_convolve_kernel(const ZBatch b,
                                                         const float2* __restrict__ tw_all) {
-    constexpr int NZH = NZ > 1 ? NZ / 2 : 1;   // stored z planes
+    constexpr int NZH = NZ > 1 ? (PZ ? NZ : NZ / 2) : 1;   // stored z planes
     constexpr int KT = NZ > 1 ? NZ / 2 + 1 : 1;  // folded kz values
     constexpr int NC = 2 * TH;                   // columns per block
     constexpr int NLN = 3 * NC;
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(NT) void z_convolve_kernel(const ZBatch b,
     if constexpr (NZ == 1) {
         for (int line = tid; line < NLN; line += NT) buf[line] = gsrc(line, 0);
     } else {
-        fft_io<NZ, -1, NLN, NT, ColLines<NLN>, true, false, true, MF>(buf, twZ, gsrc, lds_sink);
+        fft_io<NZ, -1, NLN, NT, ColLines<NLN>, !PZ, false, true, MF>(buf, twZ, gsrc, lds_sink);
     }
     // the kernel tile goes to LDS only now, so its loads overlapped the transform
 #pragma unroll
@@ -119,13 +120,38 @@ __global__ __launch_bounds__(NT) void z_convolve_kernel(const ZBatch b,
     if constexpr (NZ == 1) {
         for (int line = tid; line < NLN; line += NT) gsink(line, 0, buf[line]);
     } else {
-        fft_io<NZ, +1, NLN, NT, ColLines<NLN>, false, true, true, MF>(buf, twZ, lds_src, gsink);
+        fft_io<NZ, +1, NLN, NT, ColLines<NLN>, false, !PZ, true, MF>(buf, twZ, lds_src, gsink);
     }
 }
 
 
-int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, hipStream_t s) {
+int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, hipStream_t s,
+                      bool periodic) {
     if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "z stage: bad batch size");
+    if (periodic && Nz > 1) {
+        if (mf) return fail(DEMAG_EUNSUPPORTED, "z stage: periodic transforms are FP32 only");
+        switch (Nz) {
+#define CASE(NZv)                                                                              \
+    case NZv: {                                                                                \
+        constexpr int NZ = NZv;                                                                \
+        constexpr int TH = ZTile<NZ, 1>::TH;                                                   \
+        b.start[0] = 0;                                                                        \
+        for (int r = 0; r < b.count; ++r) {                                                    \
+            int ny = b.d[r].Ny > 1 ? b.d[r].Ny / 2 : 1;                                        \
+            int th = TH < ny ? TH : ny;                                                        \
+            b.start[r + 1] = b.start[r] + (ny / th) * b.d[r].nk;                               \
+        }                                                                                      \
+        hipLaunchKernelGGL((z_convolve_kernel<NZ, TH, 0, true>), dim3((unsigned)finish_batch(b)), \
+                           dim3(NT), 0, s, b, tw);                                             \
+        break;                                                                                 \
+    }
+            CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64) CASE(128)
+#undef CASE
+            default: return fail(DEMAG_EUNSUPPORTED, "z stage: unsupported nz");
+        }
+        DM_CHECK_LAUNCH();
+        return DEMAG_OK;
+    }
     switch (Nz) {
 #define BODY(V)                                                                                \
     {                                                                                          \

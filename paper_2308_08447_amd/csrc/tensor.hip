@@ -21,6 +21,10 @@
 //    frequencies per axis (the y/z symmetry packing of App. A).
 // 3. K = -(-1)^{#odd axes/2} ... stored as FP32: K_ab = -N^_ab/(Nx Ny Nz) with
 //    the (-i)^2 = -1 of the two odd axes of an off-diagonal component folded in.
+// Periodic axes (Sec. II: modified kernel, no padding): the transform length is
+// n_d, the octant is r_d <= n_d/2, N is the sum over the periodic images of the
+// body (tensor_image_kernel), and r_d = n_d/2, its own mirror, enters the
+// cosine sum once; the sine sums vanish there.
 #include <cmath>
 #include <vector>
 
@@ -164,19 +168,11 @@ __device__ void tensor_far(double x, double y, double z, double hx, double hy, d
     }
 }
 
-// N(r) on the octant; T0[6][nz][ny][nx].  kind 0: the cell-averaged tensor of
+// N at displacement (X, Y, Z) (units of h).  kind 0: the cell-averaged tensor of
 // Eq. (1) (Newell near, moment expansion far); kind 1: the point-dipole tensor of
 // Eq. (8), V (delta |r|^2 - 3 r r)/(4 pi |r|^5) with N(0) = 0 (site i excluded).
-__global__ void tensor_octant_kernel(double* __restrict__ T0, int nx, int ny, int nz,
-                                     double hx, double hy, double hz, int kind) {
-    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t n = (size_t)nx * ny * nz;
-    if (idx >= n) return;
-    int i = (int)(idx % nx);
-    int j = (int)((idx / nx) % ny);
-    int k = (int)(idx / ((size_t)nx * ny));
-    double X = i * hx, Y = j * hy, Z = k * hz;
-    double out[6];
+__device__ void tensor_point(double X, double Y, double Z, double hx, double hy, double hz,
+                             int kind, double* out) {
     const double r2 = X * X + Y * Y + Z * Z;
     if (kind == 1) {
         const double c = r2 > 0.0 ? hx * hy * hz / (4.0 * PI * r2 * r2 * sqrt(r2)) : 0.0;
@@ -197,7 +193,93 @@ __global__ void tensor_octant_kernel(double* __restrict__ T0, int nx, int ny, in
     } else {
         tensor_far(X, Y, Z, hx, hy, hz, out);
     }
+}
+
+// N on the octant; T0[6][nz][ny][nx].
+__global__ void tensor_octant_kernel(double* __restrict__ T0, int nx, int ny, int nz,
+                                     double hx, double hy, double hz, int kind) {
+    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t n = (size_t)nx * ny * nz;
+    if (idx >= n) return;
+    int i = (int)(idx % nx);
+    int j = (int)((idx / nx) % ny);
+    int k = (int)(idx / ((size_t)nx * ny));
+    double out[6];
+    tensor_point(i * hx, j * hy, k * hz, hx, hy, hz, kind, out);
     for (int comp = 0; comp < 6; ++comp) T0[(size_t)comp * n + idx] = out[comp];
+}
+
+// Moment expansion of the cell-pair tensor through its h^2 term,
+//   N_ab ~= -V/(4 pi) [phi_ab + sum_d h_d^2/12 phi_abdd],  phi = 1/|r|,
+// with the closed forms phi_ab = (3 x_a x_b - delta_ab r^2)/r^5 and
+//   sum_d h_d^2 phi_abdd = 105 x_a x_b S/r^9
+//       - 15 (delta_ab S + 2 (h_a^2 + h_b^2) x_a x_b + H x_a x_b)/r^7
+//       + 3 delta_ab (H + 2 h_a^2)/r^5,   S = sum_d h_d^2 x_d^2, H = sum_d h_d^2
+// (the derivative of 1/r of order four contracted over one index pair).  Its
+// relative error falls as (h/r)^4: about 1e-8 at r = 64 h.
+__device__ void tensor_h2(double x, double y, double z, double hx, double hy, double hz,
+                          double* out) {
+    const double X[3] = {x, y, z}, H2[3] = {hx * hx, hy * hy, hz * hz};
+    const double r2 = x * x + y * y + z * z;
+    const double ir2 = 1.0 / r2;
+    const double ir5 = ir2 * ir2 * sqrt(ir2);
+    const double ir7 = ir5 * ir2, ir9 = ir7 * ir2;
+    const double S = H2[0] * x * x + H2[1] * y * y + H2[2] * z * z;
+    const double Hs = H2[0] + H2[1] + H2[2];
+    const double c = -hx * hy * hz / (4.0 * PI);
+    const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
+    for (int comp = 0; comp < 6; ++comp) {
+        const int a = pa[comp], b = pb[comp];
+        const double xab = X[a] * X[b];
+        const double d = a == b ? 1.0 : 0.0;
+        const double phi = (3.0 * xab - d * r2) * ir5;
+        const double t4 = 105.0 * xab * S * ir9 -
+                          15.0 * (d * S + 2.0 * (H2[a] + H2[b]) * xab + Hs * xab) * ir7 +
+                          3.0 * d * (Hs + 2.0 * H2[a]) * ir5;
+        out[comp] = c * (phi + t4 / 12.0);
+    }
+}
+
+// Periodic image sum on the octant r_d < R_d; T0[6][Rz][Ry][Rx]:
+//   N_pbc(r) = sum_m N(r + m_x n_x hx e_x + m_y n_y hy e_y + m_z n_z hz e_z),
+// |m_d| <= P_d (P along periodic axes, 0 otherwise).  The image m = 0 is the
+// open tensor; the others use it up to RF h and the h^2 expansion beyond.  A
+// component odd in a periodic axis is zero at r_d = n_d/2 (the infinite sum is
+// odd and periodic there).
+constexpr double RF = 64.0;
+__global__ void tensor_image_kernel(double* __restrict__ T0, int Rx, int Ry, int Rz, int nx,
+                                    int ny, int nz, int pbc, int P, double hx, double hy,
+                                    double hz, int kind) {
+    const int Px = (pbc & 1) ? P : 0, Py = (pbc & 2) ? P : 0, Pz = (pbc & 4) ? P : 0;
+    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t n = (size_t)Rx * Ry * Rz;
+    if (idx >= n) return;
+    const int i = (int)(idx % Rx);
+    const int j = (int)((idx / Rx) % Ry);
+    const int k = (int)(idx / ((size_t)Rx * Ry));
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int mz = -Pz; mz <= Pz; ++mz)
+        for (int my = -Py; my <= Py; ++my)
+            for (int mx = -Px; mx <= Px; ++mx) {
+                const double X = (i + (double)mx * nx) * hx;
+                const double Y = (j + (double)my * ny) * hy;
+                const double Z = (k + (double)mz * nz) * hz;
+                double out[6];
+                const bool centre = mx == 0 && my == 0 && mz == 0;
+                if (centre || kind == 1 || X * X + Y * Y + Z * Z <= RF * RF)
+                    tensor_point(X, Y, Z, hx, hy, hz, kind, out);
+                else
+                    tensor_h2(X, Y, Z, hx, hy, hz, out);
+                for (int c = 0; c < 6; ++c) acc[c] += out[c];
+            }
+    // odd components (xy: x, y; xz: x, z; yz: y, z) at the half-period displacement
+    const bool hx0 = (pbc & 1) && nx >= 2 && nx % 2 == 0 && i == nx / 2;
+    const bool hy0 = (pbc & 2) && ny >= 2 && ny % 2 == 0 && j == ny / 2;
+    const bool hz0 = (pbc & 4) && nz >= 2 && nz % 2 == 0 && k == nz / 2;
+    if (hx0 || hy0) acc[3] = 0.0;
+    if (hx0 || hz0) acc[4] = 0.0;
+    if (hy0 || hz0) acc[5] = 0.0;
+    for (int c = 0; c < 6; ++c) T0[(size_t)c * n + idx] = acc[c];
 }
 
 // C[b][i][j] = scale * sum_r A(b,i,r) B(b,r,j), strided FP64; 64x64 tiles, 16x16 threads.
@@ -251,19 +333,22 @@ int gemm(const double* A, long as_b, long as_i, long as_r, const double* B, long
     return DEMAG_OK;
 }
 
-// Trigonometric matrix [D1][n] of one axis for even (cos) or odd (sin) parity.
-std::vector<double> trig_matrix(int n, int Nd, int D1, bool odd) {
-    std::vector<double> T((size_t)D1 * n, 0.0);
+// Trigonometric matrix [D1][R] of one axis for even (cos) or odd (sin) parity,
+// over the octant displacements r < R.  Displacement r stands for the transform
+// indices r and N_d - r: weight 2, except r = 0 and (periodic axis) r = N_d/2,
+// which occur once.
+std::vector<double> trig_matrix(int R, int Nd, int D1, bool odd) {
+    std::vector<double> T((size_t)D1 * R, 0.0);
     for (int k = 0; k < D1; ++k)
-        for (int r = 0; r < n; ++r) {
+        for (int r = 0; r < R; ++r) {
             if (Nd == 1) {
-                T[(size_t)k * n + r] = odd ? 0.0 : 1.0;
+                T[(size_t)k * R + r] = odd ? 0.0 : 1.0;
                 continue;
             }
             long t = ((long)k * r) % Nd;
             long double ang = 2.0L * 3.141592653589793238462643383279502884L * t / Nd;
-            double w = (r == 0) ? (odd ? 0.0 : 1.0) : 2.0;
-            T[(size_t)k * n + r] = w * (double)(odd ? sinl(ang) : cosl(ang));
+            double w = (r == 0) ? (odd ? 0.0 : 1.0) : (2 * r == Nd ? 1.0 : 2.0);
+            T[(size_t)k * R + r] = w * (double)(odd ? sinl(ang) : cosl(ang));
         }
     return T;
 }
@@ -279,7 +364,8 @@ struct DevBuf {
 
 int compute_kernel(const Geometry& g, double dx, double dy, double dz, int kind, float* K,
                    hipStream_t stream) {
-    const int nx = g.nx, ny = g.ny, nz = g.nz, X1 = g.X1, Y1 = g.Y1, Z1 = g.Z1;
+    // octant extents (n, or n/2 + 1 along a periodic axis)
+    const int nx = g.Rx, ny = g.Ry, nz = g.Rz, X1 = g.X1, Y1 = g.Y1, Z1 = g.Z1;
     const double h = std::fmax(dx, std::fmax(dy, dz));
     const size_t n0 = (size_t)nx * ny * nz;
     const size_t n1 = (size_t)nz * X1 * ny;
@@ -305,8 +391,13 @@ int compute_kernel(const Geometry& g, double dx, double dy, double dz, int kind,
                           hipMemcpyHostToDevice, stream));
     const double* TR = (const double*)trig.p;
 
-    hipLaunchKernelGGL(tensor_octant_kernel, dim3((unsigned)((n0 + 127) / 128)), dim3(128), 0,
-                       stream, (double*)T0.p, nx, ny, nz, dx / h, dy / h, dz / h, kind);
+    if (g.pbc)
+        hipLaunchKernelGGL(tensor_image_kernel, dim3((unsigned)((n0 + 127) / 128)), dim3(128), 0,
+                           stream, (double*)T0.p, nx, ny, nz, g.nx, g.ny, g.nz, g.pbc, g.images,
+                           dx / h, dy / h, dz / h, kind);
+    else
+        hipLaunchKernelGGL(tensor_octant_kernel, dim3((unsigned)((n0 + 127) / 128)), dim3(128), 0,
+                           stream, (double*)T0.p, nx, ny, nz, dx / h, dy / h, dz / h, kind);
     DM_CHECK_LAUNCH();
 
     // parity (x, y, z) per component: xx yy zz xy xz yz

@@ -80,3 +80,32 @@ def test_plan_bytes_formula():
         NZ = 2 * nz if nz > 1 else 1
         expect = 6 * Z1 * X1 * Y1 * 4 + 3 * NZ * ((X1 + 3) // 4) * ny * 4 * 8
         assert pkg.demag_plan_bytes((nx, ny, nz, 4e-9, 4e-9, 4e-9)) == expect, (nx, ny, nz)
+
+def test_periodic_plan_bytes_and_flags():
+    """Periodic axes: no padding (N_d = n_d, D1 = n_d/2 + 1), always the
+    five-pass form, FP32 only; an image count needs a periodic axis."""
+    for (nx, ny, nz), (px, py, pz) in [((512, 512, 16), (1, 1, 0)), ((64, 32, 8), (0, 1, 1)),
+                                       ((128, 1, 4), (1, 0, 1)), ((32, 32, 32), (1, 1, 1))]:
+        N = [v if p else (1 if v == 1 else 2 * v) for v, p in zip((nx, ny, nz), (px, py, pz))]
+        X1, Y1, Z1 = (1 if v == 1 else v // 2 + 1 for v in N)
+        s1 = 3 * nz * X1 * ny * 8
+        plane = 3 * nz * N[1] * 8
+        planes = X1 if ny == 1 else min(X1, (128 << 20) // plane)
+        expect = 6 * Z1 * X1 * Y1 * 4 + s1 + (planes * plane if ny > 1 else 0)
+        flags = pkg.pbc_flags(px, py, pz, images=3)
+        assert pkg.demag_plan_bytes((nx, ny, nz, 4e-9, 4e-9, 4e-9), flags=flags) == expect
+        assert pkg.kernel_shape((nx, ny, nz), (px, py, pz)) == (6, Z1, X1, Y1)
+    mesh = (64, 64, 4, 4e-9, 4e-9, 4e-9)
+    assert pkg.demag_plan_bytes(mesh, flags=pkg.DEMAG_PBC_X | pkg.DEMAG_BF16X3_MFMA) == 0
+    assert pkg.demag_plan_bytes(mesh, flags=5 << pkg.DEMAG_PBC_IMAGES_SHIFT) == 0
+    assert pkg.demag_plan_bytes(mesh, flags=pkg.DEMAG_PBC_Z | pkg.DEMAG_POINT_DIPOLE
+                                | pkg.DEMAG_EXTRAPOLATE_HD | (255 << 8)) > 0
+    with pytest.raises(pkg.DemagError) as e:
+        pkg.demag_setup(mesh, pkg.DEMAG_PBC_Y | pkg.DEMAG_BF16X2_MFMA)
+    assert e.value.status == pkg.DEMAG_EUNSUPPORTED
+    assert b"DEMAG_FP32" in pkg.load().demag_last_error()
+    with pytest.raises(pkg.DemagError) as e:
+        pkg.atom_setup((16, 16, 8, 0.4e-9, 4), pkg.pbc_flags(x=True, images=2))
+    assert e.value.status == pkg.DEMAG_EUNSUPPORTED
+    with pytest.raises(ValueError):
+        pkg.pbc_flags(x=True, images=256)

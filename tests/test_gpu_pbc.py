@@ -1,0 +1,219 @@
+"""Periodic boundary conditions on the GPU (Sec. II: image-sum kernel, no zero
+padding along a periodic axis) against the FP64 oracle, through the C ABI.
+
+Tolerance: relative L2 <= 2e-5 per field component (FP32 stages), as for the
+open meshes.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import demag as odemag
+from oracle import llg as ollg
+from oracle import pbc as opbc
+
+pytestmark = pytest.mark.gpu
+
+TOL = 2e-5
+RECT = (5e-9, 4e-9, 3e-9)
+
+
+@pytest.fixture(scope="module")
+def torch_dev(gpu_lib):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _flags(pkg, mask, images, extra=0):
+    return pkg.pbc_flags(*map(bool, mask), images=images) | extra
+
+
+def _field(pkg, torch, n, cell, M, flags):
+    plan = pkg.demag_setup(tuple(n) + tuple(cell), flags)
+    try:
+        assert pkg.demag_get_form(plan) == pkg.DEMAG_FORM_FIVE_PASS
+        Md = torch.from_numpy(M).cuda()
+        Hd = torch.empty_like(Md)
+        pkg.demag_field(plan, Md, Hd)
+        torch.cuda.synchronize()
+        return Hd.cpu().numpy().astype(np.float64)
+    finally:
+        pkg.demag_destroy(plan)
+
+
+# (mesh, periodic axes, images, cell): every periodic stage length from 2 to the
+# largest, periodic and open axes mixed, single-cell axes, images beyond 64 h
+# (the h^2 expansion), non-cubic cells
+CASES = [
+    ((16, 16, 2), (1, 1, 0), 2, W.CELL_4NM),
+    ((32, 8, 4), (1, 0, 0), 3, W.CELL_4NM),
+    ((8, 16, 8), (0, 1, 1), 2, RECT),
+    ((8, 8, 8), (1, 1, 1), 1, W.CELL_4NM),
+    ((64, 32, 1), (1, 1, 0), 4, W.CELL_4NM),
+    ((2, 4, 2), (1, 1, 1), 2, RECT),
+    ((1, 16, 4), (0, 1, 0), 3, W.CELL_4NM),
+    ((16, 1, 4), (1, 0, 1), 2, RECT),
+    ((4, 4, 2), (0, 0, 1), 4, W.CELL_4NM),
+    ((16, 8, 16), (0, 0, 1), 2, W.CELL_4NM),
+    ((32, 32, 4), (1, 1, 0), 8, RECT),
+    ((2048, 4, 1), (1, 0, 0), 1, W.CELL_4NM),
+    ((4, 2048, 2), (0, 1, 0), 1, W.CELL_4NM),
+    ((4, 4, 128), (0, 0, 1), 1, W.CELL_4NM),
+    ((16, 16, 4), (1, 1, 0), 0, W.CELL_4NM),
+]
+
+
+def _id(c):
+    n, mask, P, cell = c
+    return "x".join(map(str, n)) + "-pbc" + "".join(map(str, mask)) + f"-P{P}" + \
+        ("-rect" if cell == RECT else "")
+
+
+@pytest.mark.parametrize("case", CASES, ids=[_id(c) for c in CASES])
+def test_pbc_field_matches_oracle(torch_dev, case):
+    import paper_2308_08447_amd as pkg
+    n, mask, P, cell = case
+    _say("pbc field parity", _id(case))
+    M = W.magnetisation(n, seed=sum(n) + P)
+    H = _field(pkg, torch_dev, n, cell, M, _flags(pkg, mask, P))
+    Href = opbc.DemagPBC(n, cell, mask, P, workers=8)(M.astype(np.float64))
+    errs = odemag.rel_l2_per_field(H, Href)
+    _say("  rel-L2 per field", errs)
+    assert max(errs) <= TOL, errs
+
+
+def test_pbc_point_dipole_matches_oracle(torch_dev):
+    import paper_2308_08447_amd as pkg
+    n, mask, P = (16, 16, 4), (1, 1, 0), 3
+    _say("pbc point-dipole parity", n, mask, P)
+    M = W.magnetisation(n, seed=4)
+    H = _field(pkg, torch_dev, n, W.CELL_4NM, M, _flags(pkg, mask, P, pkg.DEMAG_POINT_DIPOLE))
+    Href = opbc.DemagPBC(n, W.CELL_4NM, mask, P, kind="dipole")(M.astype(np.float64))
+    errs = odemag.rel_l2_per_field(H, Href)
+    _say("  rel-L2 per field", errs)
+    assert max(errs) <= TOL, errs
+
+
+@pytest.mark.parametrize("n,mask,cell", [((16, 8, 4), (1, 1, 0), W.CELL_4NM),
+                                         ((8, 2, 4), (1, 0, 1), RECT),
+                                         ((4, 4, 4), (1, 1, 1), RECT)])
+def test_pbc_kernel_matches_oracle_spectrum(torch_dev, n, mask, cell):
+    """The packed FP32 kernel equals -N^_pbc/(NxNyNz) of the oracle."""
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    P = 3
+    _say("pbc kernel spectrum", n, mask, cell)
+    plan = pkg.demag_setup(tuple(n) + tuple(cell), _flags(pkg, mask, P))
+    try:
+        shape = pkg.kernel_shape(n, mask)
+        K = torch.empty(int(np.prod(shape)), dtype=torch.float32, device="cuda")
+        pkg.demag_get_kernel(plan, K, K.numel())
+        torch.cuda.synchronize()
+        K = K.cpu().numpy().reshape(shape).astype(np.float64)
+    finally:
+        pkg.demag_destroy(plan)
+    op = opbc.DemagPBC(n, cell, mask, P)
+    Nx, Ny, Nz = op.N
+    _, Z1, X1, Y1 = shape
+    ref = np.stack([-op.Khat[c].real[:Z1, :Y1, :X1].transpose(0, 2, 1) / (Nx * Ny * Nz)
+                    for c in range(6)])
+    err = np.abs(K - ref).max(axis=(1, 2, 3)) / np.abs(ref).max()
+    _say("  max error per component / max |K|", err)
+    assert np.all(err <= 1e-6), err
+
+
+def test_pbc_thin_film_sparse_sources(torch_dev):
+    """512x512x16 (4 nm cubes), periodic in x and y with 4 images: M non-zero in
+    400 random cells, explicit image sum at 16 sampled targets."""
+    import paper_2308_08447_amd as pkg
+    n, cell, mask, P = W.THIN_FILM["n"], W.THIN_FILM["cell"], (1, 1, 0), 4
+    _say("pbc thin film sparse sources", n, mask, P)
+    M, src, tg = W.sparse_sources(n, 400, 16, seed=21)
+    H = _field(pkg, torch_dev, n, cell, M, _flags(pkg, mask, P))
+    Mv = M[:, src[:, 2], src[:, 1], src[:, 0]]
+    ref = opbc.field_at(Mv, src, tg, n, cell, mask, P)
+    got = np.stack([H[:, z, y, x] for x, y, z in tg], 1)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    _say("  rel-L2 at targets", err)
+    assert err <= TOL
+
+
+def test_pbc_thin_film_translation_equivariance(torch_dev):
+    """Full size, any images: a cyclic shift of M along the periodic axes
+    shifts H the same way (circular convolution)."""
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    n, cell, mask, P = W.THIN_FILM["n"], W.THIN_FILM["cell"], (1, 1, 0), 32
+    _say("pbc thin film translation equivariance", n, mask, P)
+    M = W.magnetisation(n, seed=2)
+    plan = pkg.demag_setup(tuple(n) + tuple(cell), _flags(pkg, mask, P))
+    try:
+        Md = torch.from_numpy(M).cuda()
+        Ms = torch.roll(Md, shifts=(37, 301), dims=(2, 3)).contiguous()
+        H1, H2 = torch.empty_like(Md), torch.empty_like(Md)
+        pkg.demag_field(plan, Md, H1)
+        pkg.demag_field(plan, Ms, H2)
+        torch.cuda.synchronize()
+        H1s = torch.roll(H1, shifts=(37, 301), dims=(2, 3))
+        for a in range(3):
+            err = float(torch.linalg.norm(H2[a] - H1s[a]) / torch.linalg.norm(H1s[a]))
+            _say("  component", a, "rel-L2", err)
+            assert err <= TOL
+    finally:
+        pkg.demag_destroy(plan)
+
+
+@pytest.mark.parametrize("n,mask,P,extra", [((32, 16, 4), (1, 1, 0), 2, 0),
+                                            ((16, 8, 8), (1, 1, 1), 1, 0),
+                                            ((32, 1, 4), (1, 0, 0), 3, 0)])
+def test_pbc_llg_matches_oracle(torch_dev, n, mask, P, extra):
+    """RK4 with periodic demag and wrapped exchange, Zeeman field on."""
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    steps = 5
+    _say("pbc llg parity", n, mask, P, steps)
+    m0 = W.unit_vectors((n[2], n[1], n[0]), seed=17)
+    alpha, dt, Hz = 0.02, 1e-13, (1e4, -2e4, 3e4)
+    plan = pkg.demag_setup(tuple(n) + W.CELL_4NM, _flags(pkg, mask, P, extra))
+    try:
+        m = torch.from_numpy(m0).cuda()
+        pkg.llg_step(plan, m, (W.MS, W.A_EX, alpha, ollg.GAMMA, Hz), dt, steps)
+        torch.cuda.synchronize()
+        got = m.cpu().numpy().astype(np.float64)
+    finally:
+        pkg.demag_destroy(plan)
+    ref = ollg.LLG(n, W.CELL_4NM, W.MS, W.A_EX, alpha, Hzee=Hz, pbc=mask, images=P).run(
+        m0.astype(np.float64), dt, steps)
+    err = odemag.rel_l2(got, ref)
+    _say("  rel-L2 of m", err)
+    assert err <= TOL
+
+
+def test_pbc_llg_extrapolated_matches_oracle(torch_dev):
+    """Periodic plan with the extrapolated demagnetizing field (8 steps, so the
+    quartic is used)."""
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    n, mask, P, steps = (32, 16, 2), (1, 1, 0), 2, 8
+    _say("pbc extrapolated llg parity", n, mask, P, steps)
+    m0 = W.unit_vectors((n[2], n[1], n[0]), seed=19)
+    alpha, dt, Hz = 0.05, 1e-13, (0.0, 2e4, 1e4)
+    plan = pkg.demag_setup(tuple(n) + W.CELL_4NM, _flags(pkg, mask, P, pkg.DEMAG_EXTRAPOLATE_HD))
+    try:
+        m = torch.from_numpy(m0).cuda()
+        pkg.llg_step(plan, m, (W.MS, W.A_EX, alpha, ollg.GAMMA, Hz), dt, steps)
+        torch.cuda.synchronize()
+        got = m.cpu().numpy().astype(np.float64)
+    finally:
+        pkg.demag_destroy(plan)
+    ref = ollg.LLGExtrapolated(n, W.CELL_4NM, W.MS, W.A_EX, alpha, Hzee=Hz, pbc=mask,
+                               images=P).run(m0.astype(np.float64), dt, steps)
+    err = odemag.rel_l2(got, ref)
+    _say("  rel-L2 of m", err)
+    assert err <= TOL
