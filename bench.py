@@ -62,19 +62,20 @@ def counter_traffic(stage):
     return vals.get(stage)
 
 
-def geometry(n):
-    nx, ny, nz = n
-    N = [1 if v == 1 else 2 * v for v in n]
+def geometry(n, pbc=(False, False, False)):
+    """Transform lengths (2n open, n periodic, 1 for n = 1) and folded sizes."""
+    N = [v if (v == 1 or p) else 2 * v for v, p in zip(n, pbc)]
     D = [1 if v == 1 else v // 2 + 1 for v in N]
     return N, D
 
 
-def stage_bytes(n, form=5):
+def stage_bytes(n, form=5, pbc=(False, False, False)):
     """Algorithmic HBM bytes of one evaluation of each stage (inputs read once,
     outputs written once, zero padding never stored), for the five-pass form
-    (form 5) or the three-kernel thin-mesh form (form 3: x+z, y conv, z+x)."""
+    (form 5) or the three-kernel thin-mesh form (form 3: x+z, y conv, z+x);
+    pbc: periodic axes (unpadded transforms, five-pass form)."""
     nx, ny, nz = n
-    (Nx, Ny, Nz), (X1, Y1, Z1) = geometry(n)
+    (Nx, Ny, Nz), (X1, Y1, Z1) = geometry(n, pbc)
     cells = nx * ny * nz
     f = 12 * cells                   # one FP32 3-vector field
     k = 6 * Z1 * X1 * Y1 * 4         # packed real kernel
@@ -426,6 +427,35 @@ def main():
               "steps": args.warmup + args.steps,
               "note": "the first five steps evaluate every stage (history start-up)"}
 
+    # periodic in x and y with 32 images per side: set-up time (FP64 image-sum
+    # tensor), RK4 steps and per-stage H_d timing of the unpadded transforms
+    pbc = (True, True, False)
+    t_s = time.perf_counter()
+    plan_p = pkg.demag_setup(n + cell, pkg.pbc_flags(*pbc, images=32), stream=stream)
+    torch.cuda.synchronize()
+    setup_p = time.perf_counter() - t_s
+    mp = m0.clone()
+    for _ in range(args.warmup):
+        pkg.llg_step(plan_p, mp, params, cfg["dt"], 1, stream)
+    torch.cuda.synchronize()
+    pkg.demag_timing_enable(plan_p, 4 * args.steps * pkg.demag_get_chunks(plan_p))
+    tp0 = time.perf_counter()
+    for _ in range(args.steps):
+        pkg.llg_step(plan_p, mp, params, cfg["dt"], 1, stream)
+    torch.cuda.synchronize()
+    elapsed_p = time.perf_counter() - tp0
+    stages_p = pkg.demag_timing_read(plan_p)
+    pkg.demag_timing_enable(plan_p, 0)
+    pkg.demag_destroy(plan_p)
+    per_stage_p = _stage_table(stage_bytes(n, 5, pbc), stages_p, 4 * args.steps)
+    hd_p = sum(v["us_per_eval"] for k, v in per_stage_p.items() if k != "llg")
+    periodic = {"axes": "xy", "images_per_side": 32,
+                "setup_s": round(setup_p, 3),
+                "ms_per_step": round(1e3 * elapsed_p / args.steps, 4),
+                "gcells_per_s": round(4 * cells * args.steps / elapsed_p / 1e9, 3),
+                "hd_us_per_eval": round(hd_p, 1),
+                "stages": per_stage_p}
+
     # standalone demag_field throughput (not the headline; same stream, no events)
     M = (m0 * cfg["Ms"]).contiguous()
     H = torch.empty_like(M)
@@ -480,6 +510,7 @@ def main():
         "demag_field_bytes_this_form": b_form,
         "llg_cell_steps_per_s": round(cells * args.steps / elapsed, 1),
         "llg_extrapolated_hd": extrap,
+        "pbc_xy": periodic,
     }
     if not args.no_serve:
         # short sample of the serving workload (64 requests x 100 RK4 steps)
