@@ -24,7 +24,11 @@
  *    usable unless the status is DEMAG_EHIP (a HIP runtime failure).
  *  - Mesh sizes: every n_d must be 1 or a power of two, n_x and n_y at most 2048
  *    and n_z at most 128 (larger or other sizes return DEMAG_EUNSUPPORTED).
- *    The padded transform length is N_d = 2 n_d, or 1 when n_d = 1.
+ *    n_x and n_y may also be F 2^j with F = 3, 5 or 15 and j >= 1 (6, 10, 30,
+ *    ..., 480, 960, 1920): the transforms then add radix-3 and radix-5 passes;
+ *    such meshes take DEMAG_FP32 with open boundaries (other flags return
+ *    DEMAG_EUNSUPPORTED).  The padded transform length is N_d = 2 n_d, or 1
+ *    when n_d = 1 (n_d along a periodic axis).
  */
 #ifndef DEMAG_H
 #define DEMAG_H

@@ -29,11 +29,21 @@ int fail(int code, const std::string& msg) {
 }
 
 static bool pow2_or_one(int n) { return n >= 1 && (n & (n - 1)) == 0; }
+// F 2^j with F = 3, 5 or 15 and j >= 1 (radix-3/5 passes in the x and y stages)
+static bool mixed_size(int n) {
+    if (n < 2 || n % 2) return false;
+    int f = n;
+    while (f % 2 == 0) f /= 2;
+    return f == 3 || f == 5 || f == 15;
+}
 
 int make_geometry(int nx, int ny, int nz, int pbc, int images, Geometry* g) {
     if (nx < 1 || ny < 1 || nz < 1) return fail(DEMAG_EINVAL, "mesh sizes must be >= 1");
-    if (!pow2_or_one(nx) || !pow2_or_one(ny) || !pow2_or_one(nz))
-        return fail(DEMAG_EUNSUPPORTED, "mesh sizes must be 1 or a power of two");
+    if (!(pow2_or_one(nx) || mixed_size(nx)) || !(pow2_or_one(ny) || mixed_size(ny)) ||
+        !pow2_or_one(nz))
+        return fail(DEMAG_EUNSUPPORTED,
+                    "mesh sizes must be 1 or a power of two (n_x and n_y also 3, 5 or 15 "
+                    "times a power of two >= 2)");
     if (nx > 2048 || ny > 2048 || nz > 128)
         return fail(DEMAG_EUNSUPPORTED, "mesh too large (nx, ny <= 2048, nz <= 128)");
     g->nx = nx;
@@ -66,6 +76,9 @@ int check_mesh(const demag_mesh* m, Geometry* g, uint32_t flags) {
     if (!m) return fail(DEMAG_EINVAL, "mesh is NULL");
     int rc = make_geometry(m->nx, m->ny, m->nz, flag_pbc(flags), flag_images(flags), g);
     if (rc) return rc;
+    if ((mixed_size(g->nx) || mixed_size(g->ny)) && ((flags & 3) != DEMAG_FP32 || g->pbc))
+        return fail(DEMAG_EUNSUPPORTED,
+                    "meshes with a non-power-of-two size take DEMAG_FP32 and open boundaries");
     const double h[3] = {m->dx, m->dy, m->dz};
     for (double v : h)
         if (!(v > 0.0) || !std::isfinite(v)) return fail(DEMAG_EINVAL, "cell sizes must be finite and > 0");
@@ -122,7 +135,6 @@ int get_spectrum(const Geometry& g, double dx, double dy, double dz, int kind, h
     return DEMAG_OK;
 }
 
-static constexpr int TW_LMAX = 4096;   // longest padded transform (n_d <= 2048)
 static std::mutex g_tw_mu;
 static std::map<int, float2*> g_tw;    // per device; lives until the process ends
 
@@ -135,8 +147,8 @@ int device_twiddles(const float2** out) {
         *out = it->second;
         return DEMAG_OK;
     }
-    std::vector<float2> host((size_t)2 * TW_LMAX);
-    fill_twiddles(host.data(), TW_LMAX);
+    std::vector<float2> host((size_t)TW_ENTRIES);
+    fill_twiddles(host.data());
     float2* d = nullptr;
     int rc = dev_alloc((void**)&d, host.size() * sizeof(float2), "twiddles");
     if (rc) return rc;

@@ -62,7 +62,7 @@ int make_geometry(int nx, int ny, int nz, int pbc, int images, Geometry* g);
 // A launch processes a batch of up to MAXB independent work items (one mesh
 // each) that share the stage's transform length; the descriptors travel in the
 // kernel arguments, so launches need no device-side tables and can be captured
-// in graphs.  tw_all: twiddle tables, length-L table exp(-2 pi i t/L) at tw_all + L.
+// in graphs.  tw_all: the twiddle table, length-L part at tw_all + tw_offset(L).
 constexpr int MAXB = 16;
 constexpr int NVARIANTS = 3;
 
@@ -124,10 +124,21 @@ int xz_groups(int X1);  // kx groups of T
 int launch_xz_forward(XZBatch b, int nx, int nz, const float2* tw, hipStream_t s);
 int launch_yconv(YCBatch b, int ny, int Nz, const float2* tw, hipStream_t s);
 int launch_xz_inverse(XZBatch b, int nx, int nz, const float2* tw, hipStream_t s);
-// Largest transform length the twiddle table must hold for this geometry.
-int twiddle_table_length(const Geometry& g);
-// Fills the host table (2 * Lmax float2) with exp(-2 pi i t/L) at offset L.
-void fill_twiddles(float2* host, int Lmax);
+// Twiddle table: exp(-2 pi i t/L), t < L, for every supported length L <= 4096
+// (2^k and F 2^k, F = 3, 5, 15), the table of length L at tw_offset(L).  The
+// regions are disjoint: 2^k at [2^k, 2^(k+1)), 3 2^k at 8192 + 4 2^k, 5 2^k at
+// 16384 + 8 2^k, 15 2^k at 24576 + 16 2^k.
+constexpr int TW_LMAX = 4096;
+constexpr int TW_ENTRIES = 32768;
+constexpr int tw_odd_part(int n) { return (n > 0 && n % 2 == 0) ? tw_odd_part(n / 2) : n; }
+constexpr int tw_offset(int L) {
+    return tw_odd_part(L) == 1    ? L
+           : tw_odd_part(L) == 3 ? 8192 + 4 * (L / 3)
+           : tw_odd_part(L) == 5 ? 16384 + 8 * (L / 5)
+                                  : 24576 + 16 * (L / 15);
+}
+// Fills the host table (TW_ENTRIES float2).
+void fill_twiddles(float2* host);
 
 // ---- N^ set-up (tensor.hip) ---------------------------------------------------
 // Computes the packed FP32 kernel K (device) for the geometry and cell, in FP64.

@@ -1,12 +1,15 @@
-// fft_lds.h -- batched power-of-two complex FFTs held in LDS, for gfx950.
+// fft_lds.h -- batched complex FFTs held in LDS, for gfx950.
 //
 // A workgroup transforms NLINES lines of length L that sit in LDS.  Each radix
 // pass is a Stockham autosort step: butterfly j (0 <= j < L/R) of the pass with
 // current sub-transform size Ns reads x[j + r L/R] (r < R), multiplies element r
 // by W^(r (j mod Ns)) with W = exp(-+2 pi i/(Ns R)), does an R-point DFT in
 // registers and writes element r to (j/Ns) Ns R + (j mod Ns) + r Ns.  After the
-// last pass the line is in natural order.  Radices are 2..16, chosen so the
-// passes are as even as possible (e.g. 1024 = 16*8*8).
+// last pass the line is in natural order.  Power-of-two lengths use radices
+// 2..16, chosen so the passes are as even as possible (e.g. 1024 = 16*8*8).
+// Lengths F 2^k with F = 3, 5 or 15 (k >= 1) add radix-3 and radix-5 passes
+// between a first and a last power-of-two pass (e.g. 960 = 8*3*5*8), so that
+// the first pass can skip zero inputs and the last pass drop outputs.
 //
 // Twiddles come from a table of exp(-2 pi i t/L), t < L, rounded from FP64 on
 // the host, so every twiddle is correctly rounded (no recurrence, no
@@ -54,11 +57,37 @@ __device__ __forceinline__ float2 w16(int k) {
     return w;
 }
 
-// In-register DFT of size R (power of two <= 16), radix-2 decimation in time.
+// In-register DFT of size R: 3 and 5 by the symmetric-pair formulas, powers of
+// two <= 16 by radix-2 decimation in time.
 template <int R, int DIR>
 __device__ __forceinline__ void dft(float2* v) {
     if constexpr (R == 1) {
         return;
+    } else if constexpr (R == 3) {
+        // y_{1,2} = x0 - (x1 + x2)/2 +- DIR i sin(2 pi/3) (x1 - x2)
+        constexpr float s = 0.86602540378443865f;
+        float2 a = cadd(v[1], v[2]);
+        float2 d = cscale(mul_i<DIR>(csub(v[1], v[2])), s);
+        float2 t = csub(v[0], cscale(a, 0.5f));
+        v[0] = cadd(v[0], a);
+        v[1] = cadd(t, d);
+        v[2] = csub(t, d);
+    } else if constexpr (R == 5) {
+        // pairs x1 +- x4, x2 +- x3 against cos and sin of 2 pi/5 and 4 pi/5
+        constexpr float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;
+        constexpr float s1 = 0.95105651629515357f, s2 = 0.58778525229247313f;
+        float2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+        float2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+        float2 x0 = v[0];
+        float2 r1 = cadd(x0, cadd(cscale(a1, c1), cscale(a2, c2)));
+        float2 r2 = cadd(x0, cadd(cscale(a1, c2), cscale(a2, c1)));
+        float2 i1 = mul_i<DIR>(cadd(cscale(b1, s1), cscale(b2, s2)));
+        float2 i2 = mul_i<DIR>(csub(cscale(b1, s2), cscale(b2, s1)));
+        v[0] = cadd(x0, cadd(a1, a2));
+        v[1] = cadd(r1, i1);
+        v[4] = csub(r1, i1);
+        v[2] = cadd(r2, i2);
+        v[3] = csub(r2, i2);
     } else if constexpr (R == 2) {
         float2 a = v[0], b = v[1];
         v[0] = cadd(a, b);
@@ -116,16 +145,34 @@ __device__ __forceinline__ void dft_half_in(float2* v) {
 }
 
 constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+constexpr int odd_part(int n) { return (n > 0 && n % 2 == 0) ? odd_part(n / 2) : n; }
+constexpr bool is_pow2c(int n) { return odd_part(n) == 1; }
 
-// Radix of pass p for a length-L transform: ceil(log2 L / 4) passes, bits spread evenly.
-constexpr int radix_of(int L, int p) {
-    int k = ilog2c(L);
-    int P = (k + 3) / 4;
-    if (P == 0) return 1;
-    int base = k / P, extra = k % P;
-    return 1 << (base + (p < extra ? 1 : 0));
+// Power-of-two passes of 2^k: ceil(k / 4) of them, bits spread evenly; with an
+// odd factor at least two (first and last pass even) once k >= 2.
+constexpr int pow2_passes(int k, bool mixed) {
+    return (mixed && k >= 2 && (k + 3) / 4 < 2) ? 2 : (k + 3) / 4;
 }
-constexpr int npasses(int L) { return (ilog2c(L) + 3) / 4; }
+constexpr int pow2_radix(int k, int P, int q) {
+    return P == 0 ? 1 : 1 << (k / P + (q < k % P ? 1 : 0));
+}
+constexpr int odd_passes(int F) { return F == 15 ? 2 : (F == 1 ? 0 : 1); }
+
+// Radix of pass p for a length-L transform: the first power-of-two pass, then
+// the odd radices (3, 5), then the remaining power-of-two passes.
+constexpr int radix_of(int L, int p) {
+    const int F = odd_part(L), k = ilog2c(L / F), P = pow2_passes(k, F > 1);
+    const int no = odd_passes(F);
+    if (F == 1) return pow2_radix(k, P, p);
+    if (p == 0 && P > 0) return pow2_radix(k, P, 0);
+    const int q = P > 0 ? p - 1 : p;           // index among the odd passes
+    if (q < no) return F == 15 ? (q == 0 ? 3 : 5) : F;
+    return pow2_radix(k, P, q - no + 1);
+}
+constexpr int npasses(int L) {
+    const int F = odd_part(L);
+    return pow2_passes(ilog2c(L / F), F > 1) + odd_passes(F);
+}
 
 // Radix plan of the split-precision MFMA transforms (MF > 0): every pass is
 // radix 16 except a first pass that takes the remaining 2, 4 or 8 (e.g. 2048 =
@@ -153,10 +200,16 @@ constexpr int lpad_c(int i) { return i + (i >> 4); }
 // of the butterfly stride, i the butterfly's base), which is a compile-time
 // constant: with one padding element per 16, i + n never carries past a
 // 16-element boundary that n itself does not cross.
+// For other lengths the distance depends on i: at<false>(i, n) computes it.
 template <int LS>
 struct RowLines {
     static __device__ __forceinline__ int idx(int line, int i) { return line * LS + lpad(i); }
     static constexpr int off(int n) { return lpad_c(n); }
+    template <bool P2>
+    static __device__ __forceinline__ int at(int i, int n) {
+        if constexpr (P2) return lpad_c(n);
+        else return lpad(i + n) - lpad(i);
+    }
     template <int NB>
     static __device__ __forceinline__ void split(int b, int& line, int& j) { line = b / NB; j = b - line * NB; }
 };
@@ -167,6 +220,8 @@ template <int NL>
 struct ColLines {
     static __device__ __forceinline__ int idx(int line, int i) { return i * NL + line; }
     static constexpr int off(int n) { return n * NL; }
+    template <bool P2>
+    static __device__ __forceinline__ int at(int, int n) { return n * NL; }
     template <int NB>
     static __device__ __forceinline__ void split(int b, int& line, int& j) { j = b / NL; line = b - j * NL; }
 };
@@ -177,6 +232,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
     constexpr int NB = L / R;               // butterflies per line
     constexpr int TOT = NB * NLINES;
     constexpr int PER = (TOT + NT - 1) / NT;
+    constexpr bool P2 = is_pow2c(L);
     float2 v[PER][R];
     const int tid = threadIdx.x;
 #pragma unroll
@@ -187,7 +243,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
             Addr::template split<NB>(b, line, j);
             const float2* src = buf + Addr::idx(line, j);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = src[Addr::off(r * NB)];
+            for (int r = 0; r < R; ++r) v[q][r] = src[Addr::template at<P2>(j, r * NB)];
             if constexpr (NS > 1) {
                 int k = j % NS;
 #pragma unroll
@@ -208,9 +264,10 @@ __device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restr
             int line, j;
             Addr::template split<NB>(b, line, j);
             int k = j % NS;
-            float2* dst = buf + Addr::idx(line, (j / NS) * NS * R + k);
+            const int base = (j / NS) * NS * R + k;
+            float2* dst = buf + Addr::idx(line, base);
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[Addr::off(r * NS)] = v[q][r];
+            for (int r = 0; r < R; ++r) dst[Addr::template at<P2>(base, r * NS)] = v[q][r];
         }
     }
     __syncthreads();
@@ -244,6 +301,7 @@ __device__ __forceinline__ void first_pass(float2* buf, Src& src) {
     constexpr int TOT = NB * NLINES;
     constexpr int PER = (TOT + NT - 1) / NT;
     constexpr int RIN = HALF_IN ? R / 2 : R;
+    static_assert(!HALF_IN || R % 2 == 0, "a pruned first pass needs an even radix");
     float2 v[PER][R];
     const int tid = threadIdx.x;
 #pragma unroll
@@ -268,7 +326,7 @@ __device__ __forceinline__ void first_pass(float2* buf, Src& src) {
             if constexpr (TO_LDS) {
                 float2* dst = buf + Addr::idx(line, j * R);
 #pragma unroll
-                for (int r = 0; r < R; ++r) dst[Addr::off(r)] = v[q][r];
+                for (int r = 0; r < R; ++r) dst[Addr::template at<is_pow2c(L)>(j * R, r)] = v[q][r];
             }
         }
     }
@@ -280,6 +338,7 @@ template <int L, int R, int DIR, int NLINES, int NT, class Addr, bool HALF_OUT, 
 __device__ __forceinline__ void last_pass(float2* buf, const float2* __restrict__ tw, Sink& sink) {
     constexpr int NB = L / R;  // == NS of this pass
     constexpr int TOT = NB * NLINES;
+    static_assert(!HALF_OUT || R % 2 == 0, "a truncated last pass needs an even radix");
     constexpr int PER = (TOT + NT - 1) / NT;
     float2 v[PER][R];
     const int tid = threadIdx.x;
@@ -291,7 +350,7 @@ __device__ __forceinline__ void last_pass(float2* buf, const float2* __restrict_
             Addr::template split<NB>(b, line, j);
             const float2* src = buf + Addr::idx(line, j);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = src[Addr::off(r * NB)];
+            for (int r = 0; r < R; ++r) v[q][r] = src[Addr::template at<is_pow2c(L)>(j, r * NB)];
         }
     }
     if constexpr (SYNC_IO) __syncthreads();

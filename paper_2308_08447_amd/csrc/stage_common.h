@@ -101,6 +101,11 @@ int finish_batch(B& b) {  // prefix sums already in start[]; returns the grid si
 #define DM_POW2_CASES(MACRO) \
     MACRO(2) MACRO(4) MACRO(8) MACRO(16) MACRO(32) MACRO(64) MACRO(128) MACRO(256) MACRO(512) \
     MACRO(1024) MACRO(2048)
+// Mesh sizes F 2^j (F = 3, 5, 15, j >= 1) along x and y: FP32, one tile shape.
+#define DM_MIXED_CASES(MACRO)                                                                 \
+    MACRO(6) MACRO(12) MACRO(24) MACRO(48) MACRO(96) MACRO(192) MACRO(384) MACRO(768)         \
+    MACRO(1536) MACRO(10) MACRO(20) MACRO(40) MACRO(80) MACRO(160) MACRO(320) MACRO(640)      \
+    MACRO(1280) MACRO(30) MACRO(60) MACRO(120) MACRO(240) MACRO(480) MACRO(960) MACRO(1920)
 
 // The split-precision MFMA forms (mf = 2, 3) are built for the middle tile
 // variant only; plans that use them always run variant 1.

@@ -19,8 +19,8 @@ __global__ __launch_bounds__(NT) void x_forward_kernel(const XBatch b,
     constexpr int LS = lpad_c(L) + 1;  // odd stride: the pairs of one frequency hit distinct banks
     __shared__ float2 buf[NP * LS];
     __shared__ float2 twL[L];
-    const float2* tw2L = tw_all + 2 * L;
-    stage_table(twL, tw_all + L, L);
+    const float2* tw2L = tw_all + tw_offset(2 * L);
+    stage_table(twL, tw_all + tw_offset(L), L);
     const int tid = threadIdx.x;
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(NT) void x_forward_kernel(const XBatch b,
     for (int it = tid; it < (L / 2 + 1) * NP; it += NT) {
         int p = it % NP, m = it / NP;
         float2 Zk = buf[p * LS + lpad(m)];
-        float2 Zn = cconj(buf[p * LS + lpad((L - m) & (L - 1))]);
+        float2 Zn = cconj(buf[p * LS + lpad(m == 0 ? 0 : L - m)]);
         float2 Xa = cscale(cadd(Zk, Zn), 0.5f);
         float2 d = csub(Zk, Zn);
         float2 Xb = make_float2(0.5f * d.y, -0.5f * d.x);
@@ -87,8 +87,8 @@ __global__ __launch_bounds__(NT) void x_inverse_kernel(const XBatch b,
     __shared__ float2 ie[PX ? 1 : NP * LS];
     __shared__ float2 twL[L];
     __shared__ float2 tw2L[PX ? 1 : L];  // first half of the length-2L table
-    stage_table(twL, tw_all + L, L);
-    if constexpr (!PX) stage_table(tw2L, tw_all + 2 * L, L);
+    stage_table(twL, tw_all + tw_offset(L), L);
+    if constexpr (!PX) stage_table(tw2L, tw_all + tw_offset(2 * L), L);
     const int tid = threadIdx.x;
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
@@ -192,6 +192,27 @@ int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hi
         DM_CHECK_LAUNCH();
         return DEMAG_OK;
     }
+    if (!is_pow2c(nx)) {
+        if (mf) return fail(DEMAG_EUNSUPPORTED, "x stage: mixed-radix transforms are FP32 only");
+        switch (nx) {
+#define CASE(Lv)                                                                                  \
+    case Lv: {                                                                                    \
+        constexpr int L = Lv;                                                                     \
+        constexpr int TY = XTile<L, 1, false>::TY;                                                  \
+        b.start[0] = 0;                                                                           \
+        for (int r = 0; r < b.count; ++r)                                                         \
+            b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;           \
+        hipLaunchKernelGGL((x_forward_kernel<L, TY, 0, false>), dim3((unsigned)finish_batch(b)),      \
+                           dim3(NT), 0, s, b, tw);                                                \
+        break;                                                                                    \
+    }
+            DM_MIXED_CASES(CASE)
+#undef CASE
+            default: return fail(DEMAG_EUNSUPPORTED, "x stage: unsupported nx");
+        }
+        DM_CHECK_LAUNCH();
+        return DEMAG_OK;
+    }
     switch (nx) {
 #define BODY(V)                                                                               \
     {                                                                                         \
@@ -244,6 +265,27 @@ int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hi
         break;                                                                                    \
     }
             DM_POW2_CASES(CASE)
+#undef CASE
+            default: return fail(DEMAG_EUNSUPPORTED, "x stage: unsupported nx");
+        }
+        DM_CHECK_LAUNCH();
+        return DEMAG_OK;
+    }
+    if (!is_pow2c(nx)) {
+        if (mf) return fail(DEMAG_EUNSUPPORTED, "x stage: mixed-radix transforms are FP32 only");
+        switch (nx) {
+#define CASE(Lv)                                                                                  \
+    case Lv: {                                                                                    \
+        constexpr int L = Lv;                                                                     \
+        constexpr int TY = XTile<L, 1, true>::TY;                                                  \
+        b.start[0] = 0;                                                                           \
+        for (int r = 0; r < b.count; ++r)                                                         \
+            b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;           \
+        hipLaunchKernelGGL((x_inverse_kernel<L, TY, 0, false>), dim3((unsigned)finish_batch(b)),      \
+                           dim3(NT), 0, s, b, tw);                                                \
+        break;                                                                                    \
+    }
+            DM_MIXED_CASES(CASE)
 #undef CASE
             default: return fail(DEMAG_EUNSUPPORTED, "x stage: unsupported nx");
         }

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(XZShape<L>::NTA) void xz_forward_kernel(const XZBat
     __shared__ float2 buf[NPR * LS];
     __shared__ float2 tw2[L2];
     __shared__ float2 nyq[2 * Z::NPAIR];
-    stage_table_n<NTA>(tw2, tw_all + L2, L2);
+    stage_table_n<NTA>(tw2, tw_all + tw_offset(L2), L2);
     const int t = threadIdx.x;
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(XZShape<L>::NTA) void xz_forward_kernel(const XZBat
 
     // z: length-NZ transform of the NZS stored rows (upper half zero):
     // Y[2m] = DFT(x)[m], Y[2m+1] = DFT(x W_NZ^z)[m]
-    const float2* twz = tw_all + NZ;
+    const float2* twz = tw_all + tw_offset(NZ);
     if (owner) {
         float2 Y[2][NZ];
 #pragma unroll
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(NT) void yconv_kernel(const YCBatch b, const float2
     using Rows = RowLines<LS>;
     __shared__ float2 buf[3 * LS];
     __shared__ float2 tw[LNY];
-    stage_table(tw, tw_all + LNY, LNY);
+    stage_table(tw, tw_all + tw_offset(LNY), LNY);
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
     const YCDesc& d = b.d[item];
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(XZShape<L>::NTA) void xz_inverse_kernel(const XZBat
     __shared__ float2 buf[NPR * LS];
     __shared__ float2 tw2[L2];
     __shared__ float nyq[NZS];
-    stage_table_n<NTA>(tw2, tw_all + L2, L2);
+    stage_table_n<NTA>(tw2, tw_all + tw_offset(L2), L2);
     const int t = threadIdx.x;
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(XZShape<L>::NTA) void xz_inverse_kernel(const XZBat
     const float2* __restrict__ T = b.d[item].T;
     float* __restrict__ rows = b.d[item].H + ((size_t)c * NZS * ny + y) * L;
     const bool owner = t < L / 2;
-    const float2* twz = tw_all + NZ;
+    const float2* twz = tw_all + tw_offset(NZ);
 
     // z: truncated inverse, h[z] = IE[z] + W_NZ^-z IO[z] (IE, IO: inverses of the
     // even and odd kz inputs), for the two owned columns

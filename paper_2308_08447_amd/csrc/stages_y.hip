@@ -18,7 +18,7 @@ __global__ __launch_bounds__(NT) void y_forward_kernel(const YBatch b,
     constexpr int LS = lpad_c(LN);
     __shared__ float2 buf[LPB * LS];
     __shared__ float2 tw[LN];
-    stage_table(tw, tw_all + LN, LN);
+    stage_table(tw, tw_all + tw_offset(LN), LN);
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
     const float2* __restrict__ S1 = b.d[item].S1;
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(NT) void y_inverse_kernel(const YBatch b,
     constexpr int LS = lpad_c(LN);
     __shared__ float2 buf[LPB * LS];
     __shared__ float2 tw[LN];
-    stage_table(tw, tw_all + LN, LN);
+    stage_table(tw, tw_all + tw_offset(LN), LN);
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
     const float2* __restrict__ S2 = b.d[item].S2;
@@ -90,6 +90,31 @@ static int launch_y(YBatch b, int ny, int variant, int mf, const float2* tw, hip
         break;                                                                                \
     }
             DM_POW2_CASES(CASE)
+#undef CASE
+            default: return fail(DEMAG_EUNSUPPORTED, "y stage: unsupported ny");
+        }
+        DM_CHECK_LAUNCH();
+        return DEMAG_OK;
+    }
+    if (!is_pow2c(ny)) {
+        if (mf) return fail(DEMAG_EUNSUPPORTED, "y stage: mixed-radix transforms are FP32 only");
+        switch (ny) {
+#define CASE(Lv)                                                                              \
+    case Lv: {                                                                                \
+        constexpr int L = Lv;                                                                 \
+        constexpr int LPB = YTile<L, 1>::LPB;                                                 \
+        b.start[0] = 0;                                                                       \
+        for (int r = 0; r < b.count; ++r)                                                     \
+            b.start[r + 1] = b.start[r] + ((b.d[r].nk + LPB - 1) / LPB) * b.d[r].nz * 3;     \
+        if (INVERSE)                                                                          \
+            hipLaunchKernelGGL((y_inverse_kernel<L, LPB, 0, false>),                          \
+                               dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);       \
+        else                                                                                  \
+            hipLaunchKernelGGL((y_forward_kernel<L, LPB, 0, false>),                          \
+                               dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);       \
+        break;                                                                                \
+    }
+            DM_MIXED_CASES(CASE)
 #undef CASE
             default: return fail(DEMAG_EUNSUPPORTED, "y stage: unsupported ny");
         }

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(NT) void z_convolve_kernel(const ZBatch b,
     __shared__ float2 buf[NZ * NLN];
     __shared__ float ks[6 * KT * (TH + 1)];      // [comp][kz][f - f0], slot TH = Nyquist
     __shared__ float2 twZ[NZ];
-    stage_table(twZ, tw_all + NZ, NZ);
+    stage_table(twZ, tw_all + tw_offset(NZ), NZ);
     const int tid = threadIdx.x;
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
@@ -31,9 +31,9 @@ __global__ __launch_bounds__(NT) void z_convolve_kernel(const ZBatch b,
     const float* __restrict__ K = b.d[item].K;
     const int X1 = b.d[item].X1, Ny = b.d[item].Ny, Y1 = b.d[item].Y1, Z1 = b.d[item].Z1;
     const int k0 = b.d[item].k0, xc = b.d[item].xc;
-    const int ny = Ny > 1 ? Ny / 2 : 1;
+    const int ny = Ny > 1 ? Ny / 2 : 1;   // folded ky pairs (not a power of two for mixed Ny)
     const int th = TH < ny ? TH : ny;
-    const int nft = ny / th;
+    const int nft = (ny + th - 1) / th;
     const int id = gid - b.start[item];
     const int f0 = (id % nft) * th, kl = id / nft, kx = k0 + kl;
     const size_t P = (size_t)xc * Ny;  // complex elements per z plane of the chunk
@@ -41,9 +41,9 @@ __global__ __launch_bounds__(NT) void z_convolve_kernel(const ZBatch b,
     float2* col = S2 + (size_t)kl * Ny;
     const bool nyq = (f0 == 0 && Ny > 1);
     auto col_ky = [&](int j) -> int {
-        if (j < TH) return j < th ? f0 + j : -1;
+        if (j < TH) return (j < th && f0 + j < ny) ? f0 + j : -1;
         int jj = j - TH;
-        if (jj >= th) return -1;
+        if (jj >= th || f0 + jj >= ny) return -1;
         int f = f0 + jj;
         if (f == 0) return nyq ? Ny / 2 : -1;
         return Ny - f;
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(NT) void z_convolve_kernel(const ZBatch b,
         kr[q] = 0.f;
         if (it < NKL) {
             int j = it % (TH + 1), rest = it / (TH + 1), kz = rest % KT, comp = rest / KT;
-            int f = (j < TH) ? (j < th ? f0 + j : -1) : (nyq ? Ny / 2 : -1);
+            int f = (j < TH) ? ((j < th && f0 + j < ny) ? f0 + j : -1) : (nyq ? Ny / 2 : -1);
             if (f >= 0) kr[q] = K[(((size_t)comp * Z1 + kz) * X1 + kx) * Y1 + f];
         }
     }
@@ -139,7 +139,7 @@ int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, h
         for (int r = 0; r < b.count; ++r) {                                                    \
             int ny = b.d[r].Ny > 1 ? b.d[r].Ny / 2 : 1;                                        \
             int th = TH < ny ? TH : ny;                                                        \
-            b.start[r + 1] = b.start[r] + (ny / th) * b.d[r].nk;                               \
+            b.start[r + 1] = b.start[r] + ((ny + th - 1) / th) * b.d[r].nk;                   \
         }                                                                                      \
         hipLaunchKernelGGL((z_convolve_kernel<NZ, TH, 0, true>), dim3((unsigned)finish_batch(b)), \
                            dim3(NT), 0, s, b, tw);                                             \
@@ -160,7 +160,7 @@ int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, h
         for (int r = 0; r < b.count; ++r) {                                                    \
             int ny = b.d[r].Ny > 1 ? b.d[r].Ny / 2 : 1;                                        \
             int th = TH < ny ? TH : ny;                                                        \
-            b.start[r + 1] = b.start[r] + (ny / th) * b.d[r].nk;                               \
+            b.start[r + 1] = b.start[r] + ((ny + th - 1) / th) * b.d[r].nk;                   \
         }                                                                                      \
         DM_MF_DISPATCH(V, hipLaunchKernelGGL((z_convolve_kernel<NZ, TH, MFv>),                \
                            dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)          \
@@ -180,21 +180,15 @@ int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, h
     return DEMAG_OK;
 }
 
-int twiddle_table_length(const Geometry& g) {
-    int m = 2;
-    m = std::max(m, g.Nx);
-    m = std::max(m, g.Ny);
-    m = std::max(m, g.Nz);
-    return m;
-}
-
-void fill_twiddles(float2* host, int Lmax) {
-    // table for length L at offset L (L = 1, 2, 4, ..., Lmax): exp(-2 pi i t/L)
-    host[0] = make_float2(0.f, 0.f);
-    for (int L = 1; L <= Lmax; L *= 2) {
-        for (int t = 0; t < L; ++t) {
-            long double ang = -2.0L * 3.141592653589793238462643383279502884L * t / L;
-            host[L + t] = make_float2((float)cosl(ang), (float)sinl(ang));
+void fill_twiddles(float2* host) {
+    for (int i = 0; i < TW_ENTRIES; ++i) host[i] = make_float2(0.f, 0.f);
+    for (int F : {1, 3, 5, 15}) {
+        for (int L = F; L <= TW_LMAX; L *= 2) {
+            const int off = tw_offset(L);
+            for (int t = 0; t < L; ++t) {
+                long double ang = -2.0L * 3.141592653589793238462643383279502884L * t / L;
+                host[off + t] = make_float2((float)cosl(ang), (float)sinl(ang));
+            }
         }
     }
 }

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_plan_bytes_and_validation_on_host():
     assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9)) > 0
-    assert pkg.demag_plan_bytes((30, 32, 4, 4e-9, 4e-9, 4e-9)) == 0
+    assert pkg.demag_plan_bytes((28, 32, 4, 4e-9, 4e-9, 4e-9)) == 0
     assert pkg.demag_plan_bytes((32, 32, 256, 4e-9, 4e-9, 4e-9)) == 0
     assert pkg.demag_plan_bytes((32, 32, 4, -4e-9, 4e-9, 4e-9)) == 0
     assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=7) == 0
@@ -41,7 +41,7 @@ def test_plan_bytes_and_validation_on_host():
     assert x2 > 0
     assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=pkg.DEMAG_BF16X3_MFMA) == x2
     with pytest.raises(pkg.DemagError) as e:
-        pkg.demag_setup((24, 32, 4, 4e-9, 4e-9, 4e-9))
+        pkg.demag_setup((28, 32, 4, 4e-9, 4e-9, 4e-9))
     assert e.value.status == pkg.DEMAG_EUNSUPPORTED
     with pytest.raises(pkg.DemagError) as e:
         pkg.demag_setup((0, 32, 4, 4e-9, 4e-9, 4e-9))
@@ -109,3 +109,25 @@ def test_periodic_plan_bytes_and_flags():
     assert e.value.status == pkg.DEMAG_EUNSUPPORTED
     with pytest.raises(ValueError):
         pkg.pbc_flags(x=True, images=256)
+
+
+def test_mixed_radix_sizes_on_host():
+    """n_x, n_y = F 2^j (F = 3, 5, 15; j >= 1) are accepted with DEMAG_FP32 and
+    open boundaries; other sizes and flags are refused before any device work."""
+    cell = (5e-9, 5e-9, 5e-9)
+    nx, ny, nz = 480, 240, 2
+    Nx, Ny, Nz = 960, 480, 4
+    X1, Y1, Z1 = 481, 241, 3
+    plane = 3 * nz * Ny * 8
+    planes = min(X1, (128 << 20) // plane)
+    expect = 6 * Z1 * X1 * Y1 * 4 + 3 * nz * X1 * ny * 8 + planes * plane
+    assert pkg.demag_plan_bytes((nx, ny, nz) + cell) == expect
+    for n in [(6, 10, 1), (1920, 6, 2), (30, 1, 4), (1536, 1280, 1)]:
+        assert pkg.demag_plan_bytes(n + cell) > 0, n
+    for n in [(3, 8, 1), (14, 8, 1), (45, 8, 1), (8, 8, 6), (3840, 2, 1), (8, 7, 1)]:
+        assert pkg.demag_plan_bytes(n + cell) == 0, n
+    assert pkg.demag_plan_bytes((480, 240, 2) + cell, flags=pkg.DEMAG_BF16X3_MFMA) == 0
+    assert pkg.demag_plan_bytes((480, 240, 2) + cell, flags=pkg.pbc_flags(x=True, images=1)) == 0
+    with pytest.raises(pkg.DemagError) as e:
+        pkg.demag_setup((480, 240, 2) + cell, pkg.DEMAG_BF16X2_MFMA)
+    assert e.value.status == pkg.DEMAG_EUNSUPPORTED

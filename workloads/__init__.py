@@ -53,6 +53,17 @@ LARGE_FILM = dict(name="large film 1024x1024x32 (4 nm cubes)", n=(1024, 1024, 32
 ATOMISTIC = dict(name="atomistic 1024x1024x256 spins, 4^3 macrocells", n=(1024, 1024, 256),
                  a=0.4e-9, macro=4, J=1e-21, mu_s=1.0, alpha=0.05, dt=1e-15)
 SERVE_SHAPES = [(s, s, z) for s in (32, 64, 128, 256, 512) for z in (1, 2, 4, 8)]
+# Switching problem of the precision study (Sec. II, Fig. 2): 2.4 um x 1.2 um x
+# 10 nm, 5 nm cells, Ms = 800 kA/m; S state from saturation along [1,1,1] at
+# 1 MA/m ramped to zero, then H = (-20, 1, 0) kA/m for 1 ns.  A and alpha are not
+# given there: permalloy's A = 13 pJ/m and alpha = 0.02 are taken; the ramp
+# (its schedule is not given) runs in ramp_steps equal field decrements of
+# ramp_time each, then relax_time at zero field, all with alpha_prep.
+SWITCHING = dict(name="switching 480x240x2 (5 nm cells), H = (-20, 1, 0) kA/m, 1 ns",
+                 n=(480, 240, 2), cell=(5e-9, 5e-9, 5e-9), Ms=8.0e5, A=1.3e-11, alpha=0.02,
+                 H_sat=1.0e6, ramp_steps=10, ramp_time=50e-12, relax_time=500e-12,
+                 alpha_prep=0.5, dt_prep=2e-13, H_switch=(-2.0e4, 1.0e3, 0.0), t_switch=1e-9,
+                 dt_ref=1e-14, dts=(1e-13, 2e-13, 4e-13), record_every=4e-13)
 
 
 def serve_requests(count, seed):
