@@ -316,6 +316,72 @@ def atomistic_bench(pkg, args):
             "max_norm_error": norm_err}
 
 
+def switching_bench(pkg, args):
+    """The switching problem of the precision study (Sec. II, Fig. 2), 480x240x2
+    cells of 5 nm: S state, then 1 ns under H = (-20, 1, 0) kA/m at the reference
+    step (10 fs) and the coarser steps, <m> recorded every 400 fs on the device;
+    the mean relative error of each coarse trajectory against the reference."""
+    import torch
+    import workloads as W
+    from paper_2308_08447_amd import switching as sw
+    cfg = W.SWITCHING
+    n, cell = cfg["n"], cfg["cell"]
+    cells = n[0] * n[1] * n[2]
+    stream = torch.cuda.current_stream()
+    plan = pkg.demag_setup(n + cell, stream=stream)
+    try:
+        pkg.demag_autotune(plan, stream)
+        m = torch.empty((3, n[2], n[1], n[0]), dtype=torch.float32, device="cuda")
+        print("switching: S state", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        prep_steps = sw.s_state(pkg, plan, m, cfg, stream)
+        torch.cuda.synchronize()
+        t_prep = time.perf_counter() - t0
+        s0 = m.clone()
+        ms = torch.empty(3, dtype=torch.float32, device="cuda")
+        pkg.demag_field_mean(plan, s0, ms, stream)
+        recs, runs = {}, {}
+        for dt in (cfg["dt_ref"],) + tuple(cfg["dts"]):
+            print(f"switching: 1 ns at dt = {dt * 1e15:.0f} fs", file=sys.stderr, flush=True)
+            m.copy_(s0)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rec = sw.switch(pkg, plan, m, cfg, dt, stream)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t1
+            steps = int(round(cfg["t_switch"] / dt))
+            recs[dt] = rec.cpu().numpy().astype(np.float64)
+            runs[dt] = {"steps": steps, "s": round(el, 3),
+                        "ms_per_step": round(1e3 * el / steps, 4),
+                        "gcells_per_s": round(4 * cells * steps / el / 1e9, 3)}
+    finally:
+        pkg.demag_destroy(plan)
+    ref = recs[cfg["dt_ref"]]
+    for dt in cfg["dts"]:
+        runs[dt]["epsilon_vs_ref"] = float("%.3e" % sw.epsilon(recs[dt], ref))
+    t = np.arange(len(ref)) * cfg["record_every"]
+    cross = np.nonzero(ref[:, 0] < 0)[0]
+    coarse = max(cfg["dts"])
+    return {
+        "metric": "switching problem: mean relative error vs the 10 fs reference; Gcells/s",
+        "value": runs[coarse]["gcells_per_s"], "unit": "Gcells/s",
+        "n_gpus": 1, "steps": runs[coarse]["steps"], "warmup": 0,
+        "ms_per_step": runs[coarse]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": cfg["name"], "mesh": list(n), "cell_m": list(cell),
+                   "alpha": cfg["alpha"], "H_switch_A_per_m": list(cfg["H_switch"]),
+                   "s_state": {"ramp": f"{cfg['ramp_steps']} x {cfg['ramp_time'] * 1e12:.0f} ps from "
+                                       f"{cfg['H_sat'] / 1e6:.0f} MA/m along [1,1,1]",
+                               "relax_ps": cfg["relax_time"] * 1e12, "alpha": cfg["alpha_prep"],
+                               "steps": prep_steps, "s": round(t_prep, 3),
+                               "mean_m": [round(float(v), 5) for v in ms.cpu()]},
+                   "record_every_fs": cfg["record_every"] * 1e15},
+        "runs_fs": {f"{dt * 1e15:.0f}": runs[dt] for dt in runs},
+        "reference": {"first_mx_below_zero_ps": round(float(t[cross[0]]) * 1e12, 1) if len(cross) else None,
+                      "final_mean_m": [round(float(v), 5) for v in ref[-1]]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,9 +392,11 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="first run one plain device copy of MB megabytes (a known-size "
                          "reference for hardware byte counters)")
-    ap.add_argument("--workload", default="thin_film", choices=("thin_film", "large_film", "atomistic"),
+    ap.add_argument("--workload", default="thin_film",
+                    choices=("thin_film", "large_film", "atomistic", "switching"),
                     help="thin_film (default): 512x512x16 RK4 LLG; large_film: 1024x1024x32 "
-                         "demag_field; atomistic: 1024x1024x256 spins, Heun, 4^3 macrocells")
+                         "demag_field; atomistic: 1024x1024x256 spins, Heun, 4^3 macrocells; "
+                         "switching: the 480x240x2 switching problem, 1 ns at 10-400 fs steps")
     ap.add_argument("--variants", type=lambda s: [int(v) for v in s.split(",")], default=None,
                     help="pin the tile variant of the five FFT stages (e.g. 1,1,1,1,1) instead "
                          "of autotuning")
@@ -367,6 +435,9 @@ def main():
         return
     if args.workload == "atomistic":
         print(json.dumps(atomistic_bench(pkg, args)), flush=True)
+        return
+    if args.workload == "switching":
+        print(json.dumps(switching_bench(pkg, args)), flush=True)
         return
 
     cfg = W.THIN_FILM

@@ -178,6 +178,17 @@ int llg_step(demag_plan* plan, float* m, const llg_params* params, double dt,
  */
 int llg_reset(demag_plan* plan);
 
+/*
+ * demag_field_mean -- out[c] = mean over the plan's cells of component c of the
+ * field v (c = x, y, z): the average magnetization <m> recorded along a
+ * trajectory in the precision study of Sec. II (Fig. 2).  FP64 partial sums in
+ * a fixed order, so the value is reproducible bit for bit.
+ *   v    in   device, FP32 [3][nz][ny][nx].
+ *   out  out  device, 3 FP32 values; written on `stream` (no synchronisation).
+ * Errors: EINVAL (null argument), EHIP.
+ */
+int demag_field_mean(demag_plan* plan, const float* v, float* out, void* stream);
+
 /* ---- atomistic spin dynamics (Eqs. 7, 9, 10; Sec. IV) ------------------- */
 typedef struct {
     int32_t nx, ny, nz;   /* spins on a simple-cubic lattice */

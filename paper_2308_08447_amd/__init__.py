@@ -45,7 +45,8 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EUNSUPPORTED", -4: "EH
 # symbols declared in include/demag.h
 EXPORTS = (
     "demag_setup", "demag_field", "demag_plan_bytes", "demag_get_kernel", "demag_destroy",
-    "llg_step", "llg_reset", "atom_setup", "atom_step", "atom_destroy", "demag_timing_enable",
+    "llg_step", "llg_reset", "demag_field_mean", "atom_setup", "atom_step", "atom_destroy",
+    "demag_timing_enable",
     "demag_timing_read", "demag_autotune", "demag_set_variant", "demag_get_variant",
     "demag_set_chunks", "demag_get_chunks", "demag_get_form", "serve_open", "serve_submit", "serve_wait",
     "serve_get_stats", "serve_close", "demag_last_error",
@@ -118,6 +119,7 @@ def load(path=None):
         "demag_destroy": ([vp], ctypes.c_int),
         "llg_step": ([vp, vp, P(llg_params), ctypes.c_double, ctypes.c_int32, vp], ctypes.c_int),
         "llg_reset": ([vp], ctypes.c_int),
+        "demag_field_mean": ([vp, vp, vp, vp], ctypes.c_int),
         "atom_setup": ([P(atom_mesh), ctypes.c_uint32, vp, P(vp)], ctypes.c_int),
         "atom_step": ([vp, vp, P(atom_params), ctypes.c_double, ctypes.c_int32, vp], ctypes.c_int),
         "atom_destroy": ([vp], ctypes.c_int),
@@ -207,6 +209,11 @@ def llg_step(plan, m, params, dt, nsteps, stream=None):
         Ms, A, alpha, gamma, hz = params
         params = llg_params(Ms, A, alpha, gamma, (ctypes.c_double * 3)(*hz))
     return _check(load().llg_step(plan, _ptr(m), ctypes.byref(params), dt, nsteps, _stream(stream)))
+
+
+def demag_field_mean(plan, v, out, stream=None):
+    """out[0:3] (device) = mean of each component of the [3][N] field v (device)."""
+    return _check(load().demag_field_mean(plan, _ptr(v), _ptr(out), _stream(stream)))
 
 
 def llg_reset(plan):

@@ -695,6 +695,11 @@ int llg_step(demag_plan* plan, float* m, const llg_params* prm, double dt, int32
     return DEMAG_OK;
 }
 
+int demag_field_mean(demag_plan* plan, const float* v, float* out, void* stream) {
+    if (!plan || !v || !out) return fail(DEMAG_EINVAL, "plan, v and out must be non-NULL");
+    return launch_field_mean(v, plan->g.cells(), out, (hipStream_t)stream);
+}
+
 int llg_reset(demag_plan* plan) {
     if (!plan) return fail(DEMAG_EINVAL, "plan is NULL");
     plan->hist_n = 0;

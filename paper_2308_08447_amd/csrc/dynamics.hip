@@ -112,6 +112,25 @@ __global__ __launch_bounds__(256) void extrapolate_kernel(float* __restrict__ ou
     out[i] = v;
 }
 
+// Mean over the cells of each component of a [3][N] field: one 1024-thread block
+// per component, FP64 partial sums in a fixed order (strided per thread, then a
+// tree in LDS), so the result does not depend on scheduling.
+__global__ __launch_bounds__(1024) void field_mean_kernel(const float* __restrict__ v, size_t n,
+                                                          float* __restrict__ out) {
+    __shared__ double part[1024];
+    const int c = blockIdx.x, t = threadIdx.x;
+    const float* __restrict__ f = v + (size_t)c * n;
+    double acc = 0.0;
+    for (size_t i = t; i < n; i += 1024) acc += (double)f[i];
+    part[t] = acc;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (t < w) part[t] += part[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[c] = (float)(part[0] / (double)n);
+}
+
 // ---------------------------------------------------------------- atomistic
 // Eq. (9): M = mu_s mu_B/(a^3 N_S) * sum of the unit spins of the macrocell.
 __global__ __launch_bounds__(256) void macro_average_kernel(AtomArgs a, const float* __restrict__ S,
@@ -223,6 +242,12 @@ int launch_extrapolate(float* out, const float* const h[5], const float w[5], si
         e.w[j] = w[j];
     }
     hipLaunchKernelGGL(extrapolate_kernel, dim3(blocks_for(n)), dim3(256), 0, stream, out, e, n);
+    DM_CHECK_LAUNCH();
+    return DEMAG_OK;
+}
+
+int launch_field_mean(const float* v, size_t n, float* out, hipStream_t stream) {
+    hipLaunchKernelGGL(field_mean_kernel, dim3(3), dim3(1024), 0, stream, v, n, out);
     DM_CHECK_LAUNCH();
     return DEMAG_OK;
 }

@@ -166,6 +166,9 @@ int launch_llg_stage(LLGBatch b, int stage, hipStream_t stream);
 int launch_extrapolate(float* out, const float* const h[5], const float w[5], size_t n,
                        hipStream_t stream);
 
+// out[c] = mean over the n cells of component c of the [3][n] field v (device)
+int launch_field_mean(const float* v, size_t n, float* out, hipStream_t stream);
+
 struct AtomArgs {
     int nx, ny, nz, macro;
     float cex;             // J/(mu0 mu_B mu_s)

@@ -131,3 +131,18 @@ def test_mixed_radix_sizes_on_host():
     with pytest.raises(pkg.DemagError) as e:
         pkg.demag_setup((480, 240, 2) + cell, pkg.DEMAG_BF16X2_MFMA)
     assert e.value.status == pkg.DEMAG_EUNSUPPORTED
+
+
+def test_switching_epsilon_and_schedule_on_host():
+    """The mean relative error of two recorded <m> trajectories, and the
+    workload's steps dividing its recording interval."""
+    from paper_2308_08447_amd import switching as sw
+    import workloads as W
+    a = [[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.6, 0.8, 0.0]]
+    b = [[1.0, 0.0, 0.0], [0.0, 0.0, 1.0], [0.6, 0.8, 0.0]]
+    assert abs(sw.epsilon(a, b) - 2 ** 0.5 / 3) < 1e-15
+    assert sw.epsilon(a, a) == 0.0
+    cfg = W.SWITCHING
+    for dt in (cfg["dt_ref"],) + tuple(cfg["dts"]):
+        k = cfg["record_every"] / dt
+        assert abs(k - round(k)) < 1e-9
