@@ -174,7 +174,18 @@ __global__ __launch_bounds__(NT) void yconv_kernel(const YCBatch b, const float2
     const YCDesc& d = b.d[item];
     const int X1 = d.X1, Y1 = d.Y1, Z1 = d.Z1, G = d.G;
     const int id = gid - b.start[item];
-    const int kx = id % X1, kz = id / X1;
+    // Planes kz and NZ - kz share the folded tensor column: their blocks are
+    // adjacent in the grid (same XCD, same moment), so the column is fetched
+    // from HBM once; pair j = 0 holds the two self-mirrored planes 0 and NZ/2.
+    int kx, kz;
+    if constexpr (NZ == 1) {
+        kx = id;
+        kz = 0;
+    } else {
+        const int member = id & 1, t = id >> 1, j = t / X1;
+        kx = t - j * X1;
+        kz = j == 0 ? (member ? NZ / 2 : 0) : (member ? NZ - j : j);
+    }
     const size_t cstride = (size_t)NZ * G * NY * TKB;  // complex elements per component
     float2* __restrict__ col = d.T + (((size_t)kz * G + kx / TKB) * NY) * TKB + kx % TKB;
 
