@@ -165,6 +165,12 @@ typedef struct {
  * with H_eff = H_d(Ms m) + 2A/(mu0 Ms) lap(m) + Hzee (free boundaries; Eq. 4),
  * H_d recomputed at every RK stage, and |m| renormalised at the end of each step.
  *   m       in/out device FP32 [3][nz][ny][nx], unit vectors, updated in place.
+ * With nsteps >= 2 (no DEMAG_EXTRAPOLATE_HD, timing off) one step is captured
+ * as a HIP graph on a plan-private stream and replayed nsteps times on
+ * `stream`; the capture is kept in the plan and redone when m, the parameters,
+ * dt, the chunk count or a tile variant change.  The launches are those of
+ * single steps, so the result is bitwise the same; small meshes, whose steps
+ * are bound by launch overhead, gain most.
  * Errors: EINVAL (null, nsteps < 0, dt not finite, bad params), ENOMEM, EHIP.
  */
 int llg_step(demag_plan* plan, float* m, const llg_params* params, double dt,

@@ -208,6 +208,8 @@ static void free_timing(demag_plan* p) {
 void free_plan(demag_plan* p) {
     if (!p) return;
     free_timing(p);
+    if (p->step_graph) (void)hipGraphExecDestroy(p->step_graph);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     (void)hipFree(p->S1);
     if (p->S2 != p->S1) (void)hipFree(p->S2);
     (void)hipFree(p->T);
@@ -684,14 +686,60 @@ int demag_get_kernel(demag_plan* plan, float* dst, size_t count, void* stream) {
     return DEMAG_OK;
 }
 
+// Captures one RK4 step of `st` as a HIP graph, unless the plan already holds
+// the graph of the same step (same m, parameters, dt, chunks and tile variants).
+static int ensure_step_graph(demag_plan* p, const LLGStep& st) {
+    std::string key((const char*)&st.m, sizeof(st.m));
+    key.append((const char*)&st.prm, sizeof(st.prm));
+    key.append((const char*)&st.dt, sizeof(st.dt));
+    key.append((const char*)&p->nch, sizeof(p->nch));
+    key.append((const char*)p->variant, sizeof(p->variant));
+    if (p->step_graph && key == p->step_key) return DEMAG_OK;
+    int rc;
+    if ((rc = ensure_rk(p))) return rc;  // no allocation inside the capture
+    if (!p->capture_stream)
+        DM_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
+    if (p->step_graph) {
+        (void)hipGraphExecDestroy(p->step_graph);
+        p->step_graph = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    DM_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
+    rc = rk4_step_batch(&st, 1, p->capture_stream);
+    hipError_t e = hipStreamEndCapture(p->capture_stream, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(DEMAG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&p->step_graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        p->step_graph = nullptr;
+        return fail(DEMAG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    p->step_key = key;
+    return DEMAG_OK;
+}
+
 int llg_step(demag_plan* plan, float* m, const llg_params* prm, double dt, int32_t nsteps,
              void* stream) {
     if (!plan || !m) return fail(DEMAG_EINVAL, "plan and m must be non-NULL");
     int rc = check_llg_params(prm, dt, nsteps);
     if (rc) return rc;
     LLGStep st{plan, m, *prm, dt};
+    hipStream_t s = (hipStream_t)stream;
+    // Several plain RK4 steps: replay one captured step (the launches are the
+    // same, so the result is bitwise that of stepping one by one).  Timed plans
+    // and plans with an H_d history step eagerly.
+    if (nsteps >= 2 && !(plan->flags & DEMAG_EXTRAPOLATE_HD) && plan->timing_cap == 0) {
+        if ((rc = ensure_step_graph(plan, st))) return rc;
+        for (int step = 0; step < nsteps; ++step)
+            DM_HIP(hipGraphLaunch(plan->step_graph, s));
+        return DEMAG_OK;
+    }
     for (int step = 0; step < nsteps; ++step)
-        if ((rc = rk4_step_batch(&st, 1, (hipStream_t)stream))) return rc;
+        if ((rc = rk4_step_batch(&st, 1, s))) return rc;
     return DEMAG_OK;
 }
 

@@ -66,6 +66,11 @@ struct demag_plan {
     std::vector<hipEvent_t> ev[DEMAG_NSTAGES];
     int timing_n[DEMAG_NSTAGES] = {};
     int variant[5] = {1, 1, 1, 1, 1};   // tile-shape variant of each FFT stage
+    // llg_step with nsteps >= 2: one RK4 step captured as a HIP graph on a
+    // private stream and replayed; step_key identifies what the capture baked in
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t step_graph = nullptr;
+    std::string step_key;
 };
 
 namespace dm {

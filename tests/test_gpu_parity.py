@@ -459,3 +459,40 @@ def test_atomistic_matches_oracle(gpu_lib, torch_dev, n, macro, steps):
     err = odemag.rel_l2(got, ref)
     _say("  rel-L2 of S", err, " increment", odemag.rel_l2(got - S0, ref - S0))
     assert err <= TOL
+
+
+@pytest.mark.parametrize("n", [(64, 32, 4), (480, 240, 2), (512, 512, 16)],
+                         ids=lambda n: "x".join(map(str, n)))
+def test_llg_graph_replay_is_bitwise_eager(gpu_lib, torch_dev, n):
+    """llg_step with nsteps >= 2 replays a captured step: bitwise the result of
+    single eager steps, also after the parameters, the field array and the
+    chunk count change (each forces a new capture)."""
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    _say("llg graph replay", n)
+    m0 = torch.from_numpy(W.unit_vectors((n[2], n[1], n[0]), seed=23)).cuda()
+    cell = (5e-9,) * 3
+    p1 = (W.MS, W.A_EX, 0.02, ollg.GAMMA, (1e4, -2e4, 3e4))
+    p2 = (W.MS, W.A_EX, 0.3, ollg.GAMMA, (-2e4, 1e3, 0.0))
+    plan = pkg.demag_setup(n + cell)
+    try:
+        eager, graph = m0.clone(), m0.clone()
+        other = m0.clone()
+        for prm, k in ((p1, 4), (p2, 3), (p1, 2)):
+            for _ in range(k):
+                pkg.llg_step(plan, eager, prm, 1e-13, 1)
+            pkg.llg_step(plan, graph, prm, 1e-13, k)
+            pkg.llg_step(plan, other, prm, 1e-13, k)    # another array: new capture
+        torch.cuda.synchronize()
+        assert torch.equal(eager, graph)
+        assert torch.equal(eager, other)
+        if n[1] > 1:
+            pkg.demag_set_chunks(plan, min(3, pkg.kernel_shape(n)[2]))
+            a, b = eager.clone(), eager.clone()
+            for _ in range(2):
+                pkg.llg_step(plan, a, p2, 2e-13, 1)
+            pkg.llg_step(plan, b, p2, 2e-13, 2)
+            torch.cuda.synchronize()
+            assert torch.equal(a, b)
+    finally:
+        pkg.demag_destroy(plan)
