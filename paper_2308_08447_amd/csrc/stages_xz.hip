@@ -154,7 +154,8 @@ __global__ __launch_bounds__(XZShape<L>::NTA) void xz_forward_kernel(const XZBat
 }
 
 // ============================================================================ y convolution
-// One block: plane kz, column kx.  Its three component lines (length LNY = 2 ny,
+// One block: plane kz, column kx (ny <= 128; longer columns take
+// yconv_reg_kernel below).  Its three component lines (length LNY = 2 ny,
 // upper half zero) are transformed together in LDS, multiplied there by the
 // tensor (each folded value K(kz, kx, f) serves ky = f and its mirror LNY - f),
 // and inverse transformed, keeping the first ny outputs.  The column's T
@@ -235,6 +236,94 @@ __global__ __launch_bounds__(NT) void yconv_kernel(const YCBatch b, const float2
     auto from_lds = [&](int c, int i) { return buf[c * LS + lpad(i)]; };
     auto sink = [&](int c, int yy, float2 v) { col[c * cstride + (size_t)yy * TKB] = v; };
     fft_io<LNY, +1, 3, NT, Rows, false, true, true>(buf, tw, from_lds, sink);
+}
+
+// Same column work for LNY = 2 NT R (ny = 256, 512), with the radices ordered so
+// that the tensor product runs in registers: forward passes 16, 16, R and
+// inverse passes R, 16, 16.  After the forward last pass thread j holds
+// k = j + NT r (r < R) of all three component lines, which is exactly the input
+// set of butterfly j of the inverse first pass; the product sits between the
+// two in registers, with no LDS round trip.
+template <int LNY, int NZ>
+__global__ __launch_bounds__(NT) void yconv_reg_kernel(const YCBatch b, const float2* __restrict__ tw_all) {
+    constexpr int NY = LNY / 2;
+    constexpr int R = LNY / 256;
+    static_assert(R >= 2 && LNY / R == NT, "thread j owns k = j + NT r of the three lines");
+    constexpr int LS = lpad_c(LNY);
+    using Rows = RowLines<LS>;
+    __shared__ float2 buf[3 * LS];
+    __shared__ float2 tw[LNY];
+    stage_table(tw, tw_all + tw_offset(LNY), LNY);
+    const int gid = xcd_tile(blockIdx.x, gridDim.x);
+    const int item = batch_item(b, gid);
+    const YCDesc& d = b.d[item];
+    const int X1 = d.X1, Y1 = d.Y1, Z1 = d.Z1, G = d.G;
+    const int id = gid - b.start[item];
+    int kx, kz;
+    if constexpr (NZ == 1) {
+        kx = id;
+        kz = 0;
+    } else {
+        const int member = id & 1, t = id >> 1, jj = t / X1;
+        kx = t - jj * X1;
+        kz = jj == 0 ? (member ? NZ / 2 : 0) : (member ? NZ - jj : jj);
+    }
+    const size_t cstride = (size_t)NZ * G * NY * TKB;
+    float2* __restrict__ col = d.T + (((size_t)kz * G + kx / TKB) * NY) * TKB + kx % TKB;
+    const int j = threadIdx.x;
+
+    // tensor values of the thread's k = j + NT r, folded to f = min(k, LNY - k)
+    const int kzf = 2 * kz > NZ ? NZ - kz : kz;
+    const float sz = 2 * kz > NZ ? -1.f : 1.f;
+    const size_t KC = (size_t)Z1 * X1 * Y1;
+    const float* kp = d.K + ((size_t)kzf * X1 + kx) * Y1;
+    float kv[R][6], sy[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int k = j + NT * r;
+        const int f = k <= NY ? k : LNY - k;
+        sy[r] = k <= NY ? 1.f : -1.f;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) kv[r][a] = kp[a * KC + f];
+    }
+
+    auto src = [&](int c, int yy) { return col[c * cstride + (size_t)yy * TKB]; };
+    first_pass<LNY, 16, -1, 3, NT, Rows, true, false, true>(buf, src);
+    stockham_pass<LNY, 16, 16, -1, 3, NT, Rows>(buf, tw);
+    float2 v[3][R];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[c][r] = buf[c * LS + lpad(j + NT * r)];
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[c][r] = cmul(v[c][r], tw[j * r]);
+        dft<R, -1>(v[c]);
+    }
+    // H^_a = sum_b K_ab M^_b at k = j + NT r
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const float kxx = kv[r][0], kyy = kv[r][1], kzz = kv[r][2];
+        const float kxy = sy[r] * kv[r][3], kxz = sz * kv[r][4], kyz = sy[r] * sz * kv[r][5];
+        const float2 mx = v[0][r], my = v[1][r], mz = v[2][r];
+        auto dot3 = [](float a, float x, float bb, float yv, float cc, float zv) {
+            return fmaf(cc, zv, fmaf(bb, yv, a * x));
+        };
+        v[0][r] = make_float2(dot3(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3(kxx, mx.y, kxy, my.y, kxz, mz.y));
+        v[1][r] = make_float2(dot3(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3(kxy, mx.y, kyy, my.y, kyz, mz.y));
+        v[2][r] = make_float2(dot3(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3(kxz, mx.y, kyz, my.y, kzz, mz.y));
+    }
+    // inverse first pass (radix R, sub-size 1: no twiddles), Stockham order j R + r
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dft<R, +1>(v[c]);
+    __syncthreads();   // every thread has read its forward inputs
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[c * LS + lpad(j * R + r)] = v[c][r];
+    __syncthreads();
+    stockham_pass<LNY, 16, R, +1, 3, NT, Rows>(buf, tw);
+    auto sink = [&](int c, int yy, float2 val) { col[c * cstride + (size_t)yy * TKB] = val; };
+    last_pass<LNY, 16, +1, 3, NT, Rows, true, false>(buf, tw, sink);
 }
 
 // ============================================================================ xz inverse
@@ -394,7 +483,10 @@ int launch_yconv(YCBatch b, int ny, int Nz, const float2* tw, hipStream_t s) {
     bool done = false;
 #define NZ_CASE(NZv)                                                                                 \
     if (Nz == NZv) {                                                                                 \
-        hipLaunchKernelGGL((yconv_kernel<LNY, NZv>), dim3(grid), dim3(NT), 0, s, b, tw);             \
+        if constexpr (LNY >= 2 * NT)                                                                 \
+            hipLaunchKernelGGL((yconv_reg_kernel<LNY, NZv>), dim3(grid), dim3(NT), 0, s, b, tw);     \
+        else                                                                                         \
+            hipLaunchKernelGGL((yconv_kernel<LNY, NZv>), dim3(grid), dim3(NT), 0, s, b, tw);         \
         done = true;                                                                                 \
     }
 #define Y_CASE(NYv)                     \
