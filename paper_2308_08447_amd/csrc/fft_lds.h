@@ -13,7 +13,9 @@
 //
 // Twiddles come from a table of exp(-2 pi i t/L), t < L, rounded from FP64 on
 // the host, so every twiddle is correctly rounded (no recurrence, no
-// hardware sin/cos approximation).
+// hardware sin/cos approximation).  The passes take the table through any
+// indexable TW: a pointer, or an accessor that forms the value from a smaller
+// table (then within a rounding or two of the correctly rounded value).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -227,8 +229,8 @@ struct ColLines {
 };
 
 // One Stockham pass (radix R, sub-size NS) over NLINES lines of length L.
-template <int L, int R, int NS, int DIR, int NLINES, int NT, class Addr>
-__device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restrict__ tw) {
+template <int L, int R, int NS, int DIR, int NLINES, int NT, class Addr, class TW>
+__device__ __forceinline__ void stockham_pass(float2* buf, TW tw) {
     constexpr int NB = L / R;               // butterflies per line
     constexpr int TOT = NB * NLINES;
     constexpr int PER = (TOT + NT - 1) / NT;
@@ -334,8 +336,8 @@ __device__ __forceinline__ void first_pass(float2* buf, Src& src) {
 }
 
 template <int L, int R, int DIR, int NLINES, int NT, class Addr, bool HALF_OUT, bool SYNC_IO,
-          class Sink>
-__device__ __forceinline__ void last_pass(float2* buf, const float2* __restrict__ tw, Sink& sink) {
+          class Sink, class TW>
+__device__ __forceinline__ void last_pass(float2* buf, TW tw, Sink& sink) {
     constexpr int NB = L / R;  // == NS of this pass
     constexpr int TOT = NB * NLINES;
     static_assert(!HALF_OUT || R % 2 == 0, "a truncated last pass needs an even radix");
