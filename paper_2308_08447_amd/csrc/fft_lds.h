@@ -190,6 +190,24 @@ constexpr int radix_at(int L, int p) {
     }
 }
 
+// exp(-2 pi i t/L) as the product of a coarse entry t / 32 and a fine entry
+// t % 32, both correctly rounded: ceil(L/32) + 32 table entries in LDS instead
+// of L, for stages whose block count per compute unit the table would limit.
+struct Tw2 {
+    const float2* c;
+    const float2* f;
+    __device__ __forceinline__ float2 operator[](int t) const { return cmul(c[t >> 5], f[t & 31]); }
+};
+constexpr int tw2_entries(int L) { return (L + 31) / 32 + 32; }
+// Fills dst[0 .. tw2_entries(L)) from the full table (block-strided, NT threads)
+// and returns the accessor; the caller's next barrier publishes the entries.
+template <int L, int NT>
+__device__ __forceinline__ Tw2 stage_tw2(float2* dst, const float2* __restrict__ full) {
+    constexpr int NC = (L + 31) / 32;
+    for (int i = threadIdx.x; i < NC + 32; i += NT) dst[i] = i < NC ? full[32 * i] : full[i - NC];
+    return Tw2{dst, dst + NC};
+}
+
 // LDS index padding: one float2 of padding every 16 elements breaks the
 // power-of-two strides of the Stockham writes across banks.
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
@@ -275,8 +293,8 @@ __device__ __forceinline__ void stockham_pass(float2* buf, TW tw) {
     __syncthreads();
 }
 
-template <int L, int P, int NS, int DIR, int NLINES, int NT, class Addr>
-__device__ __forceinline__ void fft_passes(float2* buf, const float2* __restrict__ tw) {
+template <int L, int P, int NS, int DIR, int NLINES, int NT, class Addr, class TW>
+__device__ __forceinline__ void fft_passes(float2* buf, TW tw) {
     if constexpr (P < npasses(L)) {
         constexpr int R = radix_of(L, P);
         stockham_pass<L, R, NS, DIR, NLINES, NT, Addr>(buf, tw);
@@ -389,8 +407,8 @@ struct MfSched {
     static constexpr int GPW = (NG + NW - 1) / NW;
 };
 
-template <int L, int NS, int DIR, int NLINES, int NT, class Addr, int MF>
-__device__ __forceinline__ void mf_stockham_pass(float2* buf, const float2* __restrict__ tw,
+template <int L, int NS, int DIR, int NLINES, int NT, class Addr, int MF, class TW>
+__device__ __forceinline__ void mf_stockham_pass(float2* buf, TW tw,
                                                  const Dft16Matrix<MF>& F) {
     constexpr int NB = L / 16;
     constexpr int TOT = NB * NLINES;
@@ -484,8 +502,8 @@ __device__ __forceinline__ void mf_first_pass(float2* buf, Src& src, const Dft16
 
 // Last pass (sub-size L/16) handing its outputs to sink.
 template <int L, int DIR, int NLINES, int NT, class Addr, bool HALF_OUT, bool SYNC_IO, int MF,
-          class Sink>
-__device__ __forceinline__ void mf_last_pass(float2* buf, const float2* __restrict__ tw, Sink& sink,
+          class Sink, class TW>
+__device__ __forceinline__ void mf_last_pass(float2* buf, TW tw, Sink& sink,
                                              const Dft16Matrix<MF>& F) {
     constexpr int NB = L / 16;  // == sub-size of this pass
     constexpr int TOT = NB * NLINES;
@@ -571,8 +589,8 @@ __device__ __forceinline__ void mf_single_pass(Src& src, Sink& sink, const Dft16
     }
 }
 
-template <int L, int P, int NS, int DIR, int NLINES, int NT, class Addr, int MF>
-__device__ __forceinline__ void middle_passes(float2* buf, const float2* __restrict__ tw,
+template <int L, int P, int NS, int DIR, int NLINES, int NT, class Addr, int MF, class TW>
+__device__ __forceinline__ void middle_passes(float2* buf, TW tw,
                                               const Dft16Matrix<MF>& F) {
     if constexpr (P < npasses(L) - 1) {
         constexpr int R = radix_at<MF>(L, P);
@@ -621,9 +639,8 @@ __device__ __forceinline__ void single_pass(Src& src, Sink& sink) {
 // vector ALUs; 2 or 3 = the split-precision BF16 DFT-matrix products on MFMA
 // (see mfma_dft16).  Passes of radix < 16 always run in FP32.
 template <int L, int DIR, int NLINES, int NT, class Addr, bool HALF_IN, bool HALF_OUT,
-          bool SYNC_IO, int MF = 0, class Src, class Sink>
-__device__ __forceinline__ void fft_io(float2* buf, const float2* __restrict__ tw, Src src,
-                                       Sink sink) {
+          bool SYNC_IO, int MF = 0, class TW, class Src, class Sink>
+__device__ __forceinline__ void fft_io(float2* buf, TW tw, Src src, Sink sink) {
     constexpr int P = npasses(L);
     Dft16Matrix<MF> F;
     if constexpr (MF > 0 && L >= 16) F.template init<DIR>();
@@ -651,8 +668,8 @@ __device__ __forceinline__ void fft_io(float2* buf, const float2* __restrict__ t
 // In-place FFT of NLINES lines of length L in LDS (caller syncs before; the
 // function ends with a barrier).  DIR = -1 forward, +1 inverse (unnormalised).
 // tw points at the length-L table exp(-2 pi i t/L), t < L.
-template <int L, int DIR, int NLINES, int NT, class Addr>
-__device__ __forceinline__ void lds_fft(float2* buf, const float2* __restrict__ tw) {
+template <int L, int DIR, int NLINES, int NT, class Addr, class TW>
+__device__ __forceinline__ void lds_fft(float2* buf, TW tw) {
     if constexpr (L > 1) fft_passes<L, 0, 1, DIR, NLINES, NT, Addr>(buf, tw);
 }
 

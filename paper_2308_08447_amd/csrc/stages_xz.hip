@@ -244,14 +244,6 @@ __global__ __launch_bounds__(NT) void yconv_kernel(const YCBatch b, const float2
 // k = j + NT r (r < R) of all three component lines, which is exactly the input
 // set of butterfly j of the inverse first pass; the product sits between the
 // two in registers, with no LDS round trip.
-// exp(-2 pi i t/L) as the product of a coarse entry t / 32 and a fine entry
-// t % 32, both correctly rounded: L/32 + 32 table entries in LDS instead of L,
-// which lets five blocks share a compute unit instead of four.
-struct Tw2 {
-    const float2* c;
-    const float2* f;
-    __device__ __forceinline__ float2 operator[](int t) const { return cmul(c[t >> 5], f[t & 31]); }
-};
 template <int LNY, int NZ>
 __global__ __launch_bounds__(NT) void yconv_reg_kernel(const YCBatch b, const float2* __restrict__ tw_all) {
     constexpr int NY = LNY / 2;
@@ -260,13 +252,10 @@ __global__ __launch_bounds__(NT) void yconv_reg_kernel(const YCBatch b, const fl
     constexpr int LS = lpad_c(LNY);
     using Rows = RowLines<LS>;
     __shared__ float2 buf[3 * LS];
-    __shared__ float2 twc[LNY / 32], twf[32];
-    {
-        const float2* full = tw_all + tw_offset(LNY);
-        if (threadIdx.x < 32) twf[threadIdx.x] = full[threadIdx.x];
-        if (threadIdx.x < LNY / 32) twc[threadIdx.x] = full[32 * threadIdx.x];
-    }
-    const Tw2 tw{twc, twf};
+    // twiddles as coarse x fine products (Tw2): 26.6 KB of LDS per block, so
+    // five blocks share a compute unit instead of four
+    __shared__ float2 twt[tw2_entries(LNY)];
+    const Tw2 tw = stage_tw2<LNY, NT>(twt, tw_all + tw_offset(LNY));
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
     const YCDesc& d = b.d[item];

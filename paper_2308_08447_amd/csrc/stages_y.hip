@@ -3,6 +3,19 @@
 
 namespace dm {
 
+// Twiddle source of a length-LN y transform: the table itself in LDS, or from
+// LN = 1024 on the coarse x fine pair (Tw2), which keeps a block's LDS at about
+// the size of its lines and doubles the blocks a compute unit holds.
+template <int LN>
+__device__ __forceinline__ auto y_twiddles(float2* twt, const float2* __restrict__ tw_all) {
+    if constexpr (LN >= 1024) {
+        return stage_tw2<LN, NT>(twt, tw_all + tw_offset(LN));
+    } else {
+        stage_table(twt, tw_all + tw_offset(LN), LN);
+        return (const float2*)twt;
+    }
+}
+
 // ============================================================================ y
 // The y and z stages run over a chunk of kx planes [k0, k0 + nk) whose spectra
 // live in a chunk-sized S2 buffer [3][nz][xc][Ny] (local plane kx - k0).
@@ -17,8 +30,8 @@ __global__ __launch_bounds__(NT) void y_forward_kernel(const YBatch b,
     constexpr int LN = PY ? L : 2 * L;
     constexpr int LS = lpad_c(LN);
     __shared__ float2 buf[LPB * LS];
-    __shared__ float2 tw[LN];
-    stage_table(tw, tw_all + tw_offset(LN), LN);
+    __shared__ float2 twt[LN >= 1024 ? tw2_entries(LN) : LN];
+    const auto tw = y_twiddles<LN>(twt, tw_all);
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
     const float2* __restrict__ S1 = b.d[item].S1;
@@ -44,8 +57,8 @@ __global__ __launch_bounds__(NT) void y_inverse_kernel(const YBatch b,
     constexpr int LN = PY ? L : 2 * L;
     constexpr int LS = lpad_c(LN);
     __shared__ float2 buf[LPB * LS];
-    __shared__ float2 tw[LN];
-    stage_table(tw, tw_all + tw_offset(LN), LN);
+    __shared__ float2 twt[LN >= 1024 ? tw2_entries(LN) : LN];
+    const auto tw = y_twiddles<LN>(twt, tw_all);
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
     const float2* __restrict__ S2 = b.d[item].S2;
