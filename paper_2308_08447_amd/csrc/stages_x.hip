@@ -3,6 +3,32 @@
 
 namespace dm {
 
+// Twiddle sources of the x stages: the tables themselves in LDS, or for FP32
+// from L = 1024 on coarse x fine pairs (Tw2), so that the row buffers, not the
+// tables, set how many blocks a compute unit holds.  (The MFMA forms keep the
+// tables: the extra product raised their registers past two waves per SIMD.)
+template <int L, int MF>
+constexpr bool x_tw2() { return L >= 1024 && MF == 0; }
+template <int L, int MF>
+__device__ __forceinline__ auto x_twiddles(float2* twt, const float2* __restrict__ full) {
+    if constexpr (x_tw2<L, MF>()) {
+        return stage_tw2<L, NT>(twt, full);
+    } else {
+        stage_table(twt, full, L);
+        return (const float2*)twt;
+    }
+}
+// entries t < L of the length-2L table (the inverse's odd-part rotation)
+template <int L, int MF, bool PX>
+__device__ __forceinline__ auto x_twiddles_2l(float2* twt, const float2* __restrict__ full) {
+    if constexpr (x_tw2<L, MF>()) {
+        return stage_tw2<2 * L, NT>(twt, full);
+    } else {
+        if constexpr (!PX) stage_table(twt, full, L);
+        return (const float2*)twt;
+    }
+}
+
 // ============================================================================ x
 // One block: component c, plane z, rows y0 .. y0+TY-1 (TY/2 packed pairs).
 // Forward: each pair z = a + i b is transformed twice (even outputs: DFT of z,
@@ -18,9 +44,9 @@ __global__ __launch_bounds__(NT) void x_forward_kernel(const XBatch b,
     constexpr int NP = TY / 2;
     constexpr int LS = lpad_c(L) + 1;  // odd stride: the pairs of one frequency hit distinct banks
     __shared__ float2 buf[NP * LS];
-    __shared__ float2 twL[L];
+    __shared__ float2 twt[x_tw2<L, MF>() ? tw2_entries(L) : L];
+    const auto twL = x_twiddles<L, MF>(twt, tw_all + tw_offset(L));
     const float2* tw2L = tw_all + tw_offset(2 * L);
-    stage_table(twL, tw_all + tw_offset(L), L);
     const int tid = threadIdx.x;
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
@@ -85,10 +111,11 @@ __global__ __launch_bounds__(NT) void x_inverse_kernel(const XBatch b,
     constexpr int LS = lpad_c(L) + 1;  // odd stride: the pairs of one frequency hit distinct banks
     __shared__ float2 buf[NP * LS];
     __shared__ float2 ie[PX ? 1 : NP * LS];
-    __shared__ float2 twL[L];
-    __shared__ float2 tw2L[PX ? 1 : L];  // first half of the length-2L table
-    stage_table(twL, tw_all + tw_offset(L), L);
-    if constexpr (!PX) stage_table(tw2L, tw_all + tw_offset(2 * L), L);
+    __shared__ float2 twt[x_tw2<L, MF>() ? tw2_entries(L) : L];
+    // first half of the length-2L table
+    __shared__ float2 tw2t[PX ? 1 : (x_tw2<L, MF>() ? tw2_entries(2 * L) : L)];
+    const auto twL = x_twiddles<L, MF>(twt, tw_all + tw_offset(L));
+    const auto tw2L = x_twiddles_2l<L, MF, PX>(tw2t, tw_all + tw_offset(2 * L));
     const int tid = threadIdx.x;
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
