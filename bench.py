@@ -112,10 +112,22 @@ def cpu_baseline(n, cell, budget_s=20.0):
         times.append(time.perf_counter() - t0)
     t = float(np.median(times))
     cells = n[0] * n[1] * n[2]
+    # one evaluation on a single thread, for a per-core figure
+    op1 = odemag.DemagFFT(n, cell, workers=1)
+    t0 = time.perf_counter()
+    op1(M)
+    t1 = time.perf_counter() - t0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": cells / t / 1e9, "unit": "Gcells/s", "cores": workers, "kind": "oracle",
             "sample": f"{len(times)} FP64 H_d evaluations of the {n[0]}x{n[1]}x{n[2]} mesh "
                       f"(scipy rfftn/irfftn, workers={workers}; tensor set-up excluded), "
-                      f"median {t:.3f} s each"}
+                      f"median {t:.3f} s each",
+            "one_thread_gcells_per_s": round(cells / t1 / 1e9, 6), "cpu_model": model}
 
 
 def serve_run(pkg, reqs, rate, budget, max_active, flags):
@@ -527,6 +539,42 @@ def main():
                 "hd_us_per_eval": round(hd_p, 1),
                 "stages": per_stage_p}
 
+    # the small configuration (32x32x4): per-call latency, synchronous and
+    # pipelined; its 1.4 MB of traffic stays in the caches, so no roofline
+    n1 = W.DEMAG_SMALL["n"]
+    plan1 = pkg.demag_setup(n1 + W.DEMAG_SMALL["cell"], stream=stream)
+    M1 = torch.from_numpy(W.magnetisation(n1, 0)).to(dev)
+    H1 = torch.empty_like(M1)
+    for _ in range(20):
+        pkg.demag_field(plan1, M1, H1, stream)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(200):
+        t0 = time.perf_counter()
+        pkg.demag_field(plan1, M1, H1, stream)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    for _ in range(1000):
+        pkg.demag_field(plan1, M1, H1, stream)
+    torch.cuda.synchronize()
+    small = {"mesh": list(n1), "sync_latency_us_median": round(1e6 * float(np.median(lat)), 1),
+             "pipelined_us_per_call": round(1e3 * (time.perf_counter() - t0), 2),
+             "note": "cache-resident and launch-bound: no HBM roofline"}
+    pkg.demag_destroy(plan1)
+
+    # measured device-to-device copy bandwidth (read + write bytes / time)
+    cp_src = torch.empty(256 * 2**20, dtype=torch.float32, device=dev)
+    cp_dst = torch.empty_like(cp_src)
+    cp_dst.copy_(cp_src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        cp_dst.copy_(cp_src)
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * cp_src.numel() * 4 / (time.perf_counter() - t0) / 1e9
+    del cp_src, cp_dst
+
     # standalone demag_field throughput (not the headline; same stream, no events)
     M = (m0 * cfg["Ms"]).contiguous()
     H = torch.empty_like(M)
@@ -551,6 +599,10 @@ def main():
     # the reference byte count is the five-pass one (B5), whichever form runs
     b5 = sum(v for k, v in stage_bytes(n, 5).items() if k != "llg")
     b_form = sum(v for k, v in nbytes.items() if k != "llg")
+    # counter-measured HBM bytes of one evaluation (stored rocprofv3 runs of the
+    # current kernels), to set against B5
+    tr = [counter_traffic(k) for k in nbytes if k != "llg"]
+    counter_eval = int(sum(tr)) if tr and all(v is not None for v in tr) else None
 
     out = {
         "metric": "demag H_d evals: Gcells/s + % HBM roofline; serve p50/p99 latency",
@@ -579,6 +631,10 @@ def main():
         "demag_field_effective_frac": round(b5 / t_field / 1e9 / HBM_PEAK_GBS, 4),
         "demag_field_bytes_b5": b5,
         "demag_field_bytes_this_form": b_form,
+        "demag_field_counter_bytes": counter_eval,
+        "measured_copy_GB_per_s": round(copy_gbs, 1),
+        "demag_field_frac_of_copy": round(b5 / t_field / 1e9 / copy_gbs, 4),
+        "small_config": small,
         "llg_cell_steps_per_s": round(cells * args.steps / elapsed, 1),
         "llg_extrapolated_hd": extrap,
         "pbc_xy": periodic,
