@@ -126,3 +126,22 @@ def test_mixed_llg_matches_oracle(torch_dev):
     err = odemag.rel_l2(got, ref)
     _say("  rel-L2 of m", err)
     assert err <= TOL
+
+
+@pytest.mark.parametrize("n", [(480, 240, 2), (96, 160, 4)], ids=lambda n: "x".join(map(str, n)))
+def test_mixed_autotune_keeps_the_result(torch_dev, n):
+    """Autotuning a mixed-radix plan (one tile shape; chunk counts searched)
+    leaves its result bitwise unchanged."""
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    M = torch.from_numpy(W.magnetisation(n, seed=12)).cuda()
+    plan = pkg.demag_setup(tuple(n) + (5e-9,) * 3)
+    try:
+        H1, H2 = torch.empty_like(M), torch.empty_like(M)
+        pkg.demag_field(plan, M, H1)
+        pkg.demag_autotune(plan)
+        pkg.demag_field(plan, M, H2)
+        torch.cuda.synchronize()
+        assert torch.equal(H1, H2)
+    finally:
+        pkg.demag_destroy(plan)

@@ -217,3 +217,30 @@ def test_pbc_llg_extrapolated_matches_oracle(torch_dev):
     err = odemag.rel_l2(got, ref)
     _say("  rel-L2 of m", err)
     assert err <= TOL
+
+
+@pytest.mark.parametrize("n,mask", [((512, 512, 16), (1, 1, 0)), ((64, 32, 8), (0, 1, 1))],
+                         ids=["512x512x16-xy", "64x32x8-yz"])
+def test_pbc_autotune_and_graph_replay_keep_the_result(torch_dev, n, mask):
+    """Autotuning a periodic plan leaves its field bitwise unchanged, and the
+    replayed RK4 steps (nsteps >= 2) equal single steps bitwise."""
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    M = torch.from_numpy(W.magnetisation(n, seed=14)).cuda()
+    plan = pkg.demag_setup(tuple(n) + W.CELL_4NM, _flags(pkg, mask, 2))
+    try:
+        H1, H2 = torch.empty_like(M), torch.empty_like(M)
+        pkg.demag_field(plan, M, H1)
+        pkg.demag_autotune(plan)
+        pkg.demag_field(plan, M, H2)
+        m0 = torch.from_numpy(W.unit_vectors((n[2], n[1], n[0]), seed=15)).cuda()
+        a, b = m0.clone(), m0.clone()
+        prm = (W.MS, W.A_EX, 0.05, ollg.GAMMA, (1e4, 0.0, -1e4))
+        for _ in range(3):
+            pkg.llg_step(plan, a, prm, 1e-13, 1)
+        pkg.llg_step(plan, b, prm, 1e-13, 3)
+        torch.cuda.synchronize()
+        assert torch.equal(H1, H2)
+        assert torch.equal(a, b)
+    finally:
+        pkg.demag_destroy(plan)

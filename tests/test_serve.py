@@ -17,9 +17,10 @@ CELL = W.CELL_4NM
 def _mix(count=10, seed=5, max_steps=12):
     """Seeded request mix: small meshes of uneven size, random alpha and step count."""
     rng = np.random.default_rng(seed)
-    # thin-mesh form and five-pass form (nx < 32 or nz > 16) in one mix
+    # thin-mesh form, five-pass form (nx < 32 or nz > 16) and mixed-radix sizes
+    # (five-pass, radix-3/5 passes) in one mix
     shapes = [(32, 32, 1), (64, 32, 2), (32, 64, 4), (16, 16, 8), (64, 64, 1), (8, 8, 2), (128, 16, 1),
-              (32, 32, 32), (64, 16, 16)]
+              (32, 32, 32), (64, 16, 16), (30, 24, 2), (40, 12, 1)]
     reqs = []
     for i in range(count):
         n = shapes[int(rng.integers(len(shapes)))]
