@@ -2,9 +2,9 @@
 // atomistic Heun step (Eqs. 7, 9, 10; Sec. IV) on gfx950.
 //
 // All kernels stream [3][nz][ny][nx] FP32 fields, one thread per cell, x fastest
-// so that every component load is a coalesced row; neighbours along x come from
-// the same or adjacent cache lines and neighbours along y/z from rows the
-// neighbouring wavefronts also read (L1/L2 hits).
+// so that every component load is a coalesced row.  The RK4 stage reads its
+// neighbours along y/z from rows the neighbouring wavefronts also read (L1/L2
+// hits); the Heun stages march through z with the plane in LDS (below).
 #include "engine.h"
 
 namespace dm {
@@ -155,24 +155,71 @@ __global__ __launch_bounds__(256) void macro_average_kernel(AtomArgs a, const fl
     store3(Mm, i, Nm, make_float3(a.mscale * s.x, a.mscale * s.y, a.mscale * s.z));
 }
 
-// H = J/(mu0 mu_B mu_s) sum_nn S_j (open boundaries) + H_d(macrocell) + H_zee
-__device__ __forceinline__ float3 atom_field(const AtomArgs& a, const float* __restrict__ S,
-                                             const float* __restrict__ Hdm, size_t i, size_t N,
-                                             int x, int y, int z) {
-    float3 e = make_float3(0.f, 0.f, 0.f);
-    auto add = [&](size_t j) {
-        float3 v = load3(S, j, N);
-        e.x += v.x;
-        e.y += v.y;
-        e.z += v.z;
+// ---- Heun stages (Eq. 10 at T = 0 with the field of Eq. 7 + Eq. 9's macrocell H_d)
+// H = J/(mu0 mu_B mu_s) sum_nn S_j (open boundaries: a missing neighbour adds
+// nothing) + H_d(macrocell) + H_zee.  A block takes a MTX x MTY column tile of
+// the lattice and walks through MZC planes of it.  Each plane of the stencil
+// field F (S for the predictor, Sp for the corrector) is read from HBM once:
+// the thread's own spin goes to an LDS tile whose edge threads add the x/y
+// halo, and the z neighbours are the spins the thread itself held one plane
+// before and will hold one plane later (no gathers of whole neighbour rows and
+// planes).  Neighbours are summed in the order x-1, x+1, y-1, y+1, z-1, z+1.
+// Wide, shallow tiles (128 x 2) measured fastest.
+constexpr int MTX = 128, MTY = 2, MZC = 16;
+
+struct MarchTile {
+    float v[3][MTY + 2][MTX + 2];
+};
+
+__device__ __forceinline__ void march_fill(MarchTile& t, const AtomArgs& a, const float* __restrict__ F,
+                                           size_t N, int x0, int y0, int z, float3 own, bool inside) {
+    const int tx = threadIdx.x % MTX, ty = threadIdx.x / MTX;
+    const size_t pl = (size_t)a.nx * a.ny;
+    auto put = [&](int lx, int ly, float3 val) {
+        t.v[0][ly][lx] = val.x;
+        t.v[1][ly][lx] = val.y;
+        t.v[2][ly][lx] = val.z;
     };
-    size_t pl = (size_t)a.nx * a.ny;
-    if (x > 0) add(i - 1);
-    if (x < a.nx - 1) add(i + 1);
-    if (y > 0) add(i - a.nx);
-    if (y < a.ny - 1) add(i + a.nx);
-    if (z > 0) add(i - pl);
-    if (z < a.nz - 1) add(i + pl);
+    auto fetch = [&](int gx, int gy) -> float3 {
+        if (gx < 0 || gx >= a.nx || gy < 0 || gy >= a.ny) return make_float3(0.f, 0.f, 0.f);
+        return load3(F, (size_t)z * pl + (size_t)gy * a.nx + gx, N);
+    };
+    put(tx + 1, ty + 1, inside ? own : make_float3(0.f, 0.f, 0.f));
+    if (tx == 0) put(0, ty + 1, fetch(x0 - 1, y0 + ty));
+    if (tx == MTX - 1) put(MTX + 1, ty + 1, fetch(x0 + MTX, y0 + ty));
+    if (ty == 0) put(tx + 1, 0, fetch(x0 + tx, y0 - 1));
+    if (ty == MTY - 1) put(tx + 1, MTY + 1, fetch(x0 + tx, y0 + MTY));
+}
+
+// exchange sum of the tile cell (tx, ty) with open boundaries, then z neighbours
+__device__ __forceinline__ float3 march_sum(const MarchTile& t, const AtomArgs& a, int x, int y, int z,
+                                            float3 below, float3 above) {
+    const int tx = threadIdx.x % MTX + 1, ty = threadIdx.x / MTX + 1;
+    float3 e = make_float3(0.f, 0.f, 0.f);
+    auto add = [&](int lx, int ly) {
+        e.x += t.v[0][ly][lx];
+        e.y += t.v[1][ly][lx];
+        e.z += t.v[2][ly][lx];
+    };
+    if (x > 0) add(tx - 1, ty);
+    if (x < a.nx - 1) add(tx + 1, ty);
+    if (y > 0) add(tx, ty - 1);
+    if (y < a.ny - 1) add(tx, ty + 1);
+    if (z > 0) {
+        e.x += below.x;
+        e.y += below.y;
+        e.z += below.z;
+    }
+    if (z < a.nz - 1) {
+        e.x += above.x;
+        e.y += above.y;
+        e.z += above.z;
+    }
+    return e;
+}
+
+__device__ __forceinline__ float3 march_field(const AtomArgs& a, const float* __restrict__ Hdm, float3 e,
+                                              int x, int y, int z) {
     const int mx = a.nx / a.macro, my = a.ny / a.macro, mz = a.nz / a.macro;
     size_t Nm = (size_t)mx * my * mz;
     size_t im = ((size_t)(z / a.macro) * my + (y / a.macro)) * mx + (x / a.macro);
@@ -181,40 +228,50 @@ __device__ __forceinline__ float3 atom_field(const AtomArgs& a, const float* __r
                        a.cex * e.z + hd.z + a.hz[2]);
 }
 
-__global__ __launch_bounds__(256) void heun_predict_kernel(AtomArgs a, const float* __restrict__ S,
-                                                           const float* __restrict__ Hdm,
-                                                           float* __restrict__ f0,
-                                                           float* __restrict__ Sp) {
+// STAGE 0: predictor (F = S): f0 = f(S), Sp = S + dt f0.
+// STAGE 1: corrector (F = Sp): S = normalise(S + dt/2 (f0 + f(Sp))).
+template <int STAGE>
+__global__ __launch_bounds__(MTX * MTY) void heun_march_kernel(AtomArgs a, const float* __restrict__ F,
+                                                             const float* __restrict__ Hdm,
+                                                             float* __restrict__ f0, float* Sp_or_S) {
+    __shared__ MarchTile tile;
     const size_t N = (size_t)a.nx * a.ny * a.nz;
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / ((size_t)a.nx * a.ny));
-    float3 H = atom_field(a, S, Hdm, i, N, x, y, z);
-    float3 s = load3(S, i, N);
-    float3 f = ll_rhs(s, H, a.gam, a.alpha);
-    store3(f0, i, N, f);
-    store3(Sp, i, N, make_float3(s.x + a.dt * f.x, s.y + a.dt * f.y, s.z + a.dt * f.z));
-}
-
-// S <- normalise(S + dt/2 (f0 + f(Sp))); reads neighbours of Sp only, so S may be
-// updated in place.
-__global__ __launch_bounds__(256) void heun_correct_kernel(AtomArgs a, float* S,
-                                                           const float* __restrict__ Sp,
-                                                           const float* __restrict__ f0,
-                                                           const float* __restrict__ Hdm) {
-    const size_t N = (size_t)a.nx * a.ny * a.nz;
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / ((size_t)a.nx * a.ny));
-    float3 H = atom_field(a, Sp, Hdm, i, N, x, y, z);
-    float3 sp = load3(Sp, i, N);
-    float3 f1 = ll_rhs(sp, H, a.gam, a.alpha);
-    float3 g = load3(f0, i, N);
-    float3 s = load3(S, i, N);
-    float h = 0.5f * a.dt;
-    float3 v = make_float3(s.x + h * (g.x + f1.x), s.y + h * (g.y + f1.y), s.z + h * (g.z + f1.z));
-    float inv = rsqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
-    store3(S, i, N, make_float3(v.x * inv, v.y * inv, v.z * inv));
+    const size_t pl = (size_t)a.nx * a.ny;
+    const int tilesx = (a.nx + MTX - 1) / MTX, tilesy = (a.ny + MTY - 1) / MTY;
+    const int b = blockIdx.x;
+    const int bx = b % tilesx, by = (b / tilesx) % tilesy, bz = b / (tilesx * tilesy);
+    const int x0 = bx * MTX, y0 = by * MTY, z0 = bz * MZC;
+    const int x = x0 + threadIdx.x % MTX, y = y0 + threadIdx.x / MTX;
+    const bool inside = x < a.nx && y < a.ny;
+    const size_t col = (size_t)y * a.nx + x;
+    const int zend = min(z0 + MZC, a.nz);
+    float3 zero = make_float3(0.f, 0.f, 0.f);
+    float3 below = (inside && z0 > 0) ? load3(F, (size_t)(z0 - 1) * pl + col, N) : zero;
+    float3 cur = inside ? load3(F, (size_t)z0 * pl + col, N) : zero;
+    for (int z = z0; z < zend; ++z) {
+        float3 above = (inside && z + 1 < a.nz) ? load3(F, (size_t)(z + 1) * pl + col, N) : zero;
+        march_fill(tile, a, F, N, x0, y0, z, cur, inside);
+        __syncthreads();
+        if (inside) {
+            const size_t i = (size_t)z * pl + col;
+            float3 H = march_field(a, Hdm, march_sum(tile, a, x, y, z, below, above), x, y, z);
+            float3 f = ll_rhs(cur, H, a.gam, a.alpha);
+            if constexpr (STAGE == 0) {
+                store3(f0, i, N, f);
+                store3(Sp_or_S, i, N, make_float3(cur.x + a.dt * f.x, cur.y + a.dt * f.y, cur.z + a.dt * f.z));
+            } else {
+                float3 g = load3(f0, i, N);
+                float3 s = load3(Sp_or_S, i, N);
+                float h = 0.5f * a.dt;
+                float3 v = make_float3(s.x + h * (g.x + f.x), s.y + h * (g.y + f.y), s.z + h * (g.z + f.z));
+                float inv = rsqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
+                store3(Sp_or_S, i, N, make_float3(v.x * inv, v.y * inv, v.z * inv));
+            }
+        }
+        __syncthreads();
+        below = cur;
+        cur = above;
+    }
 }
 
 unsigned blocks_for(size_t n) { return (unsigned)((n + 255) / 256); }
@@ -259,20 +316,22 @@ int launch_macro_average(const AtomArgs& a, const float* S, float* Mm, hipStream
     return DEMAG_OK;
 }
 
+static unsigned march_blocks(const AtomArgs& a) {
+    return (unsigned)(((a.nx + MTX - 1) / MTX) * ((a.ny + MTY - 1) / MTY) * ((a.nz + MZC - 1) / MZC));
+}
+
 int launch_heun_predict(const AtomArgs& a, const float* S, const float* Hdm, float* f0, float* Sp,
                         hipStream_t stream) {
-    size_t N = (size_t)a.nx * a.ny * a.nz;
-    hipLaunchKernelGGL(heun_predict_kernel, dim3(blocks_for(N)), dim3(256), 0, stream, a, S, Hdm,
-                       f0, Sp);
+    hipLaunchKernelGGL(heun_march_kernel<0>, dim3(march_blocks(a)), dim3(MTX * MTY), 0, stream, a, S,
+                       Hdm, f0, Sp);
     DM_CHECK_LAUNCH();
     return DEMAG_OK;
 }
 
 int launch_heun_correct(const AtomArgs& a, float* S, const float* Sp, const float* f0,
                         const float* Hdm, hipStream_t stream) {
-    size_t N = (size_t)a.nx * a.ny * a.nz;
-    hipLaunchKernelGGL(heun_correct_kernel, dim3(blocks_for(N)), dim3(256), 0, stream, a, S, Sp,
-                       f0, Hdm);
+    hipLaunchKernelGGL(heun_march_kernel<1>, dim3(march_blocks(a)), dim3(MTX * MTY), 0, stream, a, Sp,
+                       Hdm, const_cast<float*>(f0), S);
     DM_CHECK_LAUNCH();
     return DEMAG_OK;
 }
