@@ -28,8 +28,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 ROOT = os.path.dirname(os.path.abspath(__file__))
 # sources whose change invalidates a stored hardware-counter measurement
 KERNEL_SOURCES = ["paper_2308_08447_amd/csrc/" + f for f in (
-    "stages_x.hip", "stages_y.hip", "stages_z.hip", "stage_common.h", "fft_lds.h", "mfma_dft.h",
-    "engine.h", "dynamics.hip")]
+    "stages_x.hip", "stages_y.hip", "stages_z.hip", "stages_xz.hip", "stage_common.h", "fft_lds.h",
+    "mfma_dft.h", "engine.h", "dynamics.hip")]
 COUNTERS = "profiles/counters_thin_film_512x512x16.md"
 
 
