@@ -180,7 +180,9 @@ def serve_bench(pkg, count, steps, loads, budget=16 << 30, max_active=64, seed=2
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     cell_steps = 0
-    for n, a, nsteps, m0 in reqs:
+    for k, (n, a, nsteps, m0) in enumerate(reqs):
+        if k % 32 == 0:
+            print(f"serve: sequential baseline, request {k} of {count}", file=sys.stderr, flush=True)
         plan = pkg.demag_setup(n + W.CELL_4NM, stream=stream)
         m = torch.from_numpy(m0).cuda()
         pkg.llg_step(plan, m, (W.MS, W.A_EX, a, 2.21276e5, (0.0, 0.0, 0.0)), 1e-13, nsteps, stream)
@@ -189,6 +191,7 @@ def serve_bench(pkg, count, steps, loads, budget=16 << 30, max_active=64, seed=2
         cell_steps += n[0] * n[1] * n[2] * nsteps
     seq_wall = time.perf_counter() - t0
     # closed loop (everything queued at t = 0): saturated throughput
+    print("serve: closed loop", file=sys.stderr, flush=True)
     wall, lat, st = serve_run(pkg, reqs, None, budget, max_active, flags)
     thr = count / wall
     out = {"requests": count, "steps_per_request": steps, "hbm_budget_GB": budget / 2**30,
@@ -199,6 +202,7 @@ def serve_bench(pkg, count, steps, loads, budget=16 << 30, max_active=64, seed=2
            "sequential_plain_cell_steps_per_s": round(cell_steps / seq_wall, 1),
            "open_loop": []}
     for f in loads:
+        print(f"serve: Poisson arrivals at {f} x the closed-loop rate", file=sys.stderr, flush=True)
         wall, lat, st = serve_run(pkg, reqs, f * thr, budget, max_active, flags)
         out["open_loop"].append({"load": f, "arrival_rate_per_s": round(f * thr, 3),
                                  "p50_s": round(float(np.percentile(lat, 50)), 4),
