@@ -62,6 +62,12 @@ enum {
      * tolerance as DEMAG_FP32. */
     DEMAG_BF16X2_MFMA = 1,    /* two-term split, 3 products per DFT step */
     DEMAG_BF16X3_MFMA = 2,    /* three-term split, 6 products per DFT step */
+    /* May be or-ed with the others: demag_field accepts H == M (the field
+     * overwrites the magnetisation).  Every form reads all of M into the plan's
+     * spectral workspace in its first kernel and writes H in its last, in
+     * stream order, so the aliasing is safe; without the flag H == M is
+     * refused as a likely mistake. */
+    DEMAG_INPLACE = 4,
     /* May be or-ed with one of the above.  llg_step evaluates H_d once per RK4
      * step, at the step start, and takes the values at the sub-steps
      * (t + dt/2 twice, t + dt) from the quartic in time through the five most
@@ -117,7 +123,8 @@ typedef struct demag_plan demag_plan;   /* opaque; owns N^ and the FFT workspace
  * FFT workspace.
  *   mesh    in   mesh description (copied).
  *   flags   in   DEMAG_FP32, DEMAG_BF16X2_MFMA or DEMAG_BF16X3_MFMA (one of them),
- *                optionally or-ed with DEMAG_EXTRAPOLATE_HD and DEMAG_POINT_DIPOLE;
+ *                optionally or-ed with DEMAG_INPLACE, DEMAG_EXTRAPOLATE_HD and
+ *                DEMAG_POINT_DIPOLE;
  *                with DEMAG_FP32 also DEMAG_PBC_X/Y/Z | DEMAG_PBC_IMAGES(P).
  *   stream  in   hipStream_t used for the set-up kernels; the call synchronises it.
  *   out     out  receives the new plan (NULL on failure).
@@ -129,8 +136,9 @@ int demag_setup(const demag_mesh* mesh, uint32_t flags, void* stream, demag_plan
  * demag_field -- H = H_d(M) of Eq. (1): x R2C -> y FFT -> (z FFT, N^.M^, z IFFT)
  * -> y IFFT -> x C2R (App. A execution order, without the inter-GPU transfers).
  *   M  in   device, FP32 [3][nz][ny][nx], A/m.
- *   H  out  device, FP32 [3][nz][ny][nx], A/m; must not alias M.
- * Errors: EINVAL (null plan/pointer, H == M), EHIP.
+ *   H  out  device, FP32 [3][nz][ny][nx], A/m; may be M only for a plan set up
+ *           with DEMAG_INPLACE.
+ * Errors: EINVAL (null plan/pointer, H == M without DEMAG_INPLACE), EHIP.
  */
 int demag_field(demag_plan* plan, const float* M, float* H, void* stream);
 

@@ -24,6 +24,7 @@ DEMAG_EBUSY = -5
 DEMAG_FP32 = 0
 DEMAG_BF16X2_MFMA = 1   # radix-16 passes as 2-term split BF16 MFMA products
 DEMAG_BF16X3_MFMA = 2   # 3-term split
+DEMAG_INPLACE = 4         # demag_field may write H over M
 DEMAG_EXTRAPOLATE_HD = 8  # one H_d per RK4 step, quartic extrapolation at the sub-steps
 DEMAG_POINT_DIPOLE = 16   # point-dipole kernel of the lattice dipole-dipole field (Eq. 8)
 DEMAG_PBC_X = 32          # periodic axes (image-sum kernel, no padding; FP32 only)

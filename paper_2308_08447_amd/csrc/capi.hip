@@ -627,8 +627,8 @@ struct atom_plan {
 
 static bool valid_flags(uint32_t flags) {
     const uint32_t pbc = DEMAG_PBC_X | DEMAG_PBC_Y | DEMAG_PBC_Z;
-    const uint32_t prec = flags & ~(uint32_t)(DEMAG_EXTRAPOLATE_HD | DEMAG_POINT_DIPOLE | pbc |
-                                              (0xffu << DEMAG_PBC_IMAGES_SHIFT));
+    const uint32_t prec = flags & ~(uint32_t)(DEMAG_INPLACE | DEMAG_EXTRAPOLATE_HD | DEMAG_POINT_DIPOLE |
+                                              pbc | (0xffu << DEMAG_PBC_IMAGES_SHIFT));
     if (prec != DEMAG_FP32 && prec != DEMAG_BF16X2_MFMA && prec != DEMAG_BF16X3_MFMA) return false;
     if ((flags & pbc) == 0) return (flags >> DEMAG_PBC_IMAGES_SHIFT) == 0;  // images need an axis
     return prec == DEMAG_FP32;  // the periodic stages exist in FP32 only
@@ -672,7 +672,8 @@ int demag_destroy(demag_plan* plan) {
 int demag_field(demag_plan* plan, const float* M, float* H, void* stream) {
     if (!plan) return fail(DEMAG_EINVAL, "plan is NULL");
     if (!M || !H) return fail(DEMAG_EINVAL, "M and H must be non-NULL device pointers");
-    if ((const void*)M == (const void*)H) return fail(DEMAG_EINVAL, "H must not alias M");
+    if ((const void*)M == (const void*)H && !(plan->flags & DEMAG_INPLACE))
+        return fail(DEMAG_EINVAL, "H aliases M: set up the plan with DEMAG_INPLACE to allow it");
     const float one_scale = 1.0f;
     return run_fields(&plan, &M, &H, &one_scale, 1, (hipStream_t)stream);
 }

@@ -146,3 +146,12 @@ def test_switching_epsilon_and_schedule_on_host():
     for dt in (cfg["dt_ref"],) + tuple(cfg["dts"]):
         k = cfg["record_every"] / dt
         assert abs(k - round(k)) < 1e-9
+
+
+def test_inplace_flag_on_host():
+    """DEMAG_INPLACE combines with every other flag and does not change the
+    plan's memory; an unknown bit is still refused."""
+    mesh = (64, 32, 4, 4e-9, 4e-9, 4e-9)
+    for f in (0, pkg.DEMAG_BF16X3_MFMA, pkg.DEMAG_EXTRAPOLATE_HD, pkg.pbc_flags(x=True, images=2)):
+        assert pkg.demag_plan_bytes(mesh, flags=f | pkg.DEMAG_INPLACE) == pkg.demag_plan_bytes(mesh, flags=f) > 0
+    assert pkg.demag_plan_bytes(mesh, flags=1 << 30) == 0

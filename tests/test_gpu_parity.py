@@ -576,3 +576,26 @@ def test_thin_film_1000_steps_energy_and_extrapolation(gpu_lib, torch_dev):
         assert all(e1 <= e0 for e0, e1 in zip(e, e[1:]))
     assert max(abs(x - y) / abs(x) for x, y in zip(ea, eb)) < 1e-2
     assert eps[0] < 1e-6 and eps[1] < 1e-5
+
+
+@pytest.mark.parametrize("n,flags", [((512, 512, 16), 0), ((16, 8, 32), 0), ((64, 32, 8), 2),
+                                     ((32, 16, 4), "pbc"), ((480, 240, 2), 0)],
+                         ids=["thin", "five-pass", "bf16x3", "periodic", "mixed-radix"])
+def test_inplace_field_equals_out_of_place(gpu_lib, torch_dev, n, flags):
+    """With DEMAG_INPLACE, demag_field(M, M) leaves bitwise the field that
+    demag_field(M, H) writes to a separate array."""
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    if flags == "pbc":
+        flags = pkg.pbc_flags(x=True, y=True, images=2)
+    M = torch.from_numpy(W.magnetisation(n, seed=41)).cuda()
+    plan = pkg.demag_setup(tuple(n) + (5e-9,) * 3, flags | pkg.DEMAG_INPLACE)
+    try:
+        H = torch.empty_like(M)
+        pkg.demag_field(plan, M, H)
+        A = M.clone()
+        pkg.demag_field(plan, A, A)
+        torch.cuda.synchronize()
+        assert torch.equal(A, H)
+    finally:
+        pkg.demag_destroy(plan)
