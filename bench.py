@@ -270,8 +270,7 @@ def large_film_bench(pkg, args):
     H = torch.empty_like(M)
     b5 = sum(v for k, v in stage_bytes(n).items() if k != "llg")
     modes = {}
-    for flags, name in ((0, "fp32"), (pkg.DEMAG_BF16X2_MFMA, "bf16x2_mfma"),
-                        (pkg.DEMAG_BF16X3_MFMA, "bf16x3_mfma")):
+    for flags, name in ((0, "fp32"), (pkg.DEMAG_BF16X3_MFMA, "bf16x3_mfma")):
         t_field, per_stage, nch = _field_run(pkg, n, cell, flags, M, H32 if flags == 0 else H,
                                              args, stream, f"large film {name}")
         entry = {"Gcells_per_s": round(cells / t_field / 1e9, 3), "ms_per_eval": round(1e3 * t_field, 4),

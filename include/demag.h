@@ -60,7 +60,13 @@ enum {
      * products accumulated in FP32; twiddles, passes of radix < 16, the
      * tensor product and all data stay FP32.  Same result definition and
      * tolerance as DEMAG_FP32. */
-    DEMAG_BF16X2_MFMA = 1,    /* two-term split, 3 products per DFT step */
+    /* Two-term split (3 products per DFT step): REFUSED by demag_setup with
+     * DEMAG_EUNSUPPORTED (demag_plan_bytes returns 0).  Its error follows the
+     * largest spectral values, so where the field is small against them (a
+     * few sparse sources seen from far away) it exceeds rel-L2 2e-5 (6.4e-4
+     * measured on a 1024x1024x32 film with 400 sources).  The value stays
+     * reserved so that it is never reused for another meaning. */
+    DEMAG_BF16X2_MFMA = 1,
     DEMAG_BF16X3_MFMA = 2,    /* three-term split, 6 products per DFT step */
     /* May be or-ed with the others: demag_field accepts H == M (the field
      * overwrites the magnetisation).  Every form reads all of M into the plan's
@@ -122,7 +128,7 @@ typedef struct demag_plan demag_plan;   /* opaque; owns N^ and the FFT workspace
  * real components in FP32 packed by the y and z symmetries, and allocates the
  * FFT workspace.
  *   mesh    in   mesh description (copied).
- *   flags   in   DEMAG_FP32, DEMAG_BF16X2_MFMA or DEMAG_BF16X3_MFMA (one of them),
+ *   flags   in   DEMAG_FP32 or DEMAG_BF16X3_MFMA (DEMAG_BF16X2_MFMA is refused),
  *                optionally or-ed with DEMAG_INPLACE, DEMAG_EXTRAPOLATE_HD and
  *                DEMAG_POINT_DIPOLE;
  *                with DEMAG_FP32 also DEMAG_PBC_X/Y/Z | DEMAG_PBC_IMAGES(P).
@@ -158,6 +164,10 @@ int demag_get_kernel(demag_plan* plan, float* dst, size_t count, void* stream);
 int demag_destroy(demag_plan* plan);
 
 /* ---- micromagnetic LLG (Eqs. 4, 5; RK4 of Sec. III) --------------------- */
+/* The integrator is chosen by the entry point, not by a parameter field:
+ * llg_step always integrates with classic RK4 (the micromagnetic scheme of
+ * Sec. III) and atom_step always with Heun (the atomistic scheme of Sec. IV),
+ * so neither parameter struct carries an integrator selector. */
 typedef struct {
     double Ms;        /* saturation magnetisation, A/m (> 0) */
     double A;         /* exchange stiffness, J/m (Eq. 4) */

@@ -8,8 +8,10 @@
 // parts of the inputs.  Both operands are split into BF16 terms,
 //     v = v0 + v1 (+ v2),  v0 = bf16(v),  v1 = bf16(v - v0),  v2 = bf16(v - v0 - v1),
 // each difference exact in FP32, and the products of the leading terms are
-// accumulated in FP32: MF = 2 takes F0X0 + F0X1 + F1X0 (3 products per step), MF
-// = 3 adds F0X2 + F1X1 + F2X0 (6 products).  BF16 has FP32's exponent range, so
+// accumulated in FP32: MF = 3 takes F0X0 + F0X1 + F1X0 + F0X2 + F1X1 + F2X0 (6
+// products per step).  The library builds MF = 3 only: the two-term form
+// (first three products) misses rel-L2 2e-5 where the field is small against
+// the largest spectral values.  BF16 has FP32's exponent range, so
 // no per-line scaling is needed for field values.
 //
 // Lane layout of the 32x32x16 MFMA (wave64; lane l, n = l % 32, h = l / 32):

@@ -333,9 +333,11 @@ int serve_wait(demag_server* s, uint64_t id, float* m_out_host, double* latency_
         auto it = s->reqs.find(id);
         if (it == s->reqs.end()) return dm::fail(DEMAG_EINVAL, "unknown request id");
         r = it->second;
+        // the wait releases the lock: a concurrent serve_submit may insert into
+        // (and rehash) the map, so the iterator is not used after it
         s->cv_done.wait(lk, [&] { return r->state == Request::DONE || s->stop; });
         if (r->state != Request::DONE) return dm::fail(DEMAG_EBUSY, "server closed before the request finished");
-        s->reqs.erase(it);
+        s->reqs.erase(id);
     }
     std::copy(r->host.begin(), r->host.end(), m_out_host);
     if (latency_s) latency_s[0] = std::chrono::duration<double>(r->t_done - r->t_submit).count();

@@ -79,12 +79,12 @@ struct YTile { static constexpr int LPB = 2 * L >= (1024 << V) ? 1 : (1024 << V)
 template <int NZ, int V>
 struct ZTile { static constexpr int TH = (256 << V) / NZ < 1 ? 1 : (256 << V) / NZ; };
 
-// Calls f with the MF form as a compile-time constant (0 for variants other than 1).
+// Calls f with the MF form as a compile-time constant (0 for variants other than
+// 1): 0 (FP32) or 3 (three-term split BF16 products).
 template <int V, class F>
 void mf_dispatch(int mf, F&& f) {
     if constexpr (V == 1) {
-        if (mf == 2) f(std::integral_constant<int, 2>{});
-        else if (mf == 3) f(std::integral_constant<int, 3>{});
+        if (mf == 3) f(std::integral_constant<int, 3>{});
         else f(std::integral_constant<int, 0>{});
     } else {
         f(std::integral_constant<int, 0>{});
@@ -107,7 +107,7 @@ int finish_batch(B& b) {  // prefix sums already in start[]; returns the grid si
     MACRO(1536) MACRO(10) MACRO(20) MACRO(40) MACRO(80) MACRO(160) MACRO(320) MACRO(640)      \
     MACRO(1280) MACRO(30) MACRO(60) MACRO(120) MACRO(240) MACRO(480) MACRO(960) MACRO(1920)
 
-// The split-precision MFMA forms (mf = 2, 3) are built for the middle tile
+// The split-precision MFMA form (mf = 3) is built for the middle tile
 // variant only; plans that use them always run variant 1.
 #define DM_VARIANTS(BODY)        \
     if (mf) variant = 1;         \

@@ -36,10 +36,15 @@ def test_plan_bytes_and_validation_on_host():
     assert pkg.demag_plan_bytes((32, 32, 4, -4e-9, 4e-9, 4e-9)) == 0
     assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=7) == 0
     assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=3) == 0
-    # the two split-precision MFMA forms need the same memory
-    x2 = pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=pkg.DEMAG_BF16X2_MFMA)
-    assert x2 > 0
-    assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=pkg.DEMAG_BF16X3_MFMA) == x2
+    # the split-precision MFMA form needs the FP32 five-pass workspace; the
+    # two-term split is refused (no plan, no bytes)
+    x3 = pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=pkg.DEMAG_BF16X3_MFMA)
+    assert x3 > 0
+    assert pkg.demag_plan_bytes((32, 32, 4, 4e-9, 4e-9, 4e-9), flags=pkg.DEMAG_BF16X2_MFMA) == 0
+    with pytest.raises(pkg.DemagError) as e:
+        pkg.demag_setup((32, 32, 4, 4e-9, 4e-9, 4e-9), pkg.DEMAG_BF16X2_MFMA)
+    assert e.value.status == pkg.DEMAG_EUNSUPPORTED
+    assert b"BF16X2" in pkg.load().demag_last_error()
     with pytest.raises(pkg.DemagError) as e:
         pkg.demag_setup((28, 32, 4, 4e-9, 4e-9, 4e-9))
     assert e.value.status == pkg.DEMAG_EUNSUPPORTED
