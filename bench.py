@@ -235,6 +235,7 @@ def _field_run(pkg, n, cell, flags, M, H, args, stream, label):
     try:
         pkg.demag_autotune(plan, stream)
         nch = pkg.demag_get_chunks(plan)
+        form = pkg.demag_get_form(plan)
         print(f"{label}: timing", file=sys.stderr, flush=True)
         for _ in range(args.warmup):
             pkg.demag_field(plan, M, H, stream)
@@ -252,7 +253,7 @@ def _field_run(pkg, n, cell, flags, M, H, args, stream, label):
         t_field = (time.perf_counter() - t1) / args.steps
     finally:
         pkg.demag_destroy(plan)
-    return t_field, _stage_table(stage_bytes(n), stages, args.steps), nch
+    return t_field, _stage_table(stage_bytes(n, form), stages, args.steps), nch
 
 
 def large_film_bench(pkg, args):
@@ -293,6 +294,22 @@ def large_film_bench(pkg, args):
                         "frac": round(per_stage[dom]["GB_per_s"] / HBM_PEAK_GBS, 4), "traffic": None},
            "modes": modes}
     return out
+
+
+def field_bench(pkg, args):
+    """demag_field alone on an nx x ny x nz mesh of 4 nm cubes, seeded random unit
+    M x Ms: per-stage event timing and wall time per evaluation (a short,
+    self-contained command for profiler runs)."""
+    import torch
+    import workloads as W
+    n = tuple(int(v) for v in args.mesh.split(","))
+    cells = n[0] * n[1] * n[2]
+    stream = torch.cuda.current_stream()
+    M = torch.from_numpy(W.magnetisation(n, 0)).cuda()
+    H = torch.empty_like(M)
+    t_field, per_stage, nch = _field_run(pkg, n, W.CELL_4NM, 0, M, H, args, stream, f"field {n}")
+    return {"workload": "field", "mesh": list(n), "Gcells_per_s": round(cells / t_field / 1e9, 3),
+            "us_per_eval": round(1e6 * t_field, 1), "yz_chunks": nch, "stages": per_stage}
 
 
 def atomistic_bench(pkg, args):
@@ -408,10 +425,13 @@ def main():
                     help="first run one plain device copy of MB megabytes (a known-size "
                          "reference for hardware byte counters)")
     ap.add_argument("--workload", default="thin_film",
-                    choices=("thin_film", "large_film", "atomistic", "switching"),
+                    choices=("thin_film", "large_film", "atomistic", "switching", "field"),
                     help="thin_film (default): 512x512x16 RK4 LLG; large_film: 1024x1024x32 "
                          "demag_field; atomistic: 1024x1024x256 spins, Heun, 4^3 macrocells; "
-                         "switching: the 480x240x2 switching problem, 1 ns at 10-400 fs steps")
+                         "switching: the 480x240x2 switching problem, 1 ns at 10-400 fs steps; "
+                         "field: demag_field alone on --mesh (for profiler runs)")
+    ap.add_argument("--mesh", default="512,512,16",
+                    help="field workload: cells nx,ny,nz (4 nm cubes)")
     ap.add_argument("--variants", type=lambda s: [int(v) for v in s.split(",")], default=None,
                     help="pin the tile variant of the five FFT stages (e.g. 1,1,1,1,1) instead "
                          "of autotuning")
@@ -447,6 +467,9 @@ def main():
 
     if args.workload == "large_film":
         print(json.dumps(large_film_bench(pkg, args)), flush=True)
+        return
+    if args.workload == "field":
+        print(json.dumps(field_bench(pkg, args)), flush=True)
         return
     if args.workload == "atomistic":
         print(json.dumps(atomistic_bench(pkg, args)), flush=True)
