@@ -187,3 +187,75 @@ def test_extrapolated_rk4_keeps_fourth_order():
         assert e_extr <= 2.0 * e_plain, (dt, e_extr, e_plain)
         errs.append(e_extr)
     assert errs[0] / errs[1] > 10 and errs[1] / errs[2] > 10, errs
+
+
+def _num_grad(E, x, idx, eps):
+    """Central difference of the scalar E at the entries idx of x (exact up to
+    rounding for a quadratic E)."""
+    g = []
+    for i in idx:
+        xp, xm = x.copy(), x.copy()
+        xp[i] += eps
+        xm[i] -= eps
+        g.append((E(xp) - E(xm)) / (2 * eps))
+    return np.array(g)
+
+
+@pytest.mark.parametrize("pbc", [(False, False, False), (True, False, True)])
+def test_exchange_field_is_the_energy_gradient(pbc):
+    """Eq. (4) from the exchange energy it derives from: E = A int |grad m|^2 dV,
+    discretised as A V sum over neighbour pairs |m_j - m_i|^2 / h^2 (each pair
+    once, pairs across a periodic boundary included), so that
+    H_ex = -dE/dm_i / (mu0 Ms V).  The field is differentiated numerically from
+    the energy, so the prefactor 2A/(mu0 Ms) and the free-boundary rule are
+    checked, not restated."""
+    n = (6, 5, 4)
+    cell = (4e-9, 3e-9, 2.5e-9)
+    V = cell[0] * cell[1] * cell[2]
+    rng = np.random.default_rng(11)
+    m = rng.standard_normal((3, n[2], n[1], n[0]))
+
+    def energy(mm):
+        e = 0.0
+        for axis, h, per in ((3, cell[0], pbc[0]), (2, cell[1], pbc[1]), (1, cell[2], pbc[2])):
+            d = np.diff(mm, axis=axis)
+            e += np.sum(d * d) / h**2
+            if per:
+                first = np.take(mm, [0], axis=axis)
+                last = np.take(mm, [mm.shape[axis] - 1], axis=axis)
+                e += np.sum((first - last) ** 2) / h**2
+        return W.A_EX * V * e
+
+    H = llg.exchange_field(m, cell, W.A_EX, W.MS, pbc=pbc)
+    idx = [(c, z, y, x) for c in range(3) for (z, y, x) in
+           ((0, 0, 0), (3, 4, 5), (1, 2, 3), (0, 4, 2), (2, 0, 5))]
+    g = _num_grad(energy, m, idx, 1e-3)
+    expect = -g / (llg.MU0 * W.MS * V)
+    got = np.array([H[i] for i in idx])
+    np.testing.assert_allclose(got, expect, rtol=1e-6, atol=1e-6 * np.abs(expect).max())
+
+
+def test_atomistic_exchange_is_the_energy_gradient():
+    """Eq. (7) from the Heisenberg energy E = -J sum over nearest-neighbour pairs
+    S_i . S_j (open boundaries): H_i = -dE/dS_i / (mu0 mu_s mu_B), with mu_B the
+    Bohr magneton; differentiated numerically."""
+    n = (5, 4, 3)
+    J, mu_s = 1e-21, 2.0
+    mu_b = 9.2740100783e-24  # Bohr magneton, J/T (CODATA 2018)
+    rng = np.random.default_rng(12)
+    S = rng.standard_normal((3, n[2], n[1], n[0]))
+
+    def energy(s):
+        e = 0.0
+        for axis in (1, 2, 3):
+            a = np.take(s, range(s.shape[axis] - 1), axis=axis)
+            b = np.take(s, range(1, s.shape[axis]), axis=axis)
+            e += np.sum(a * b)
+        return -J * e
+
+    H = atomistic.exchange_field(S, J, mu_s)
+    idx = [(c, z, y, x) for c in range(3) for (z, y, x) in ((0, 0, 0), (1, 2, 3), (2, 3, 4), (1, 0, 2))]
+    g = _num_grad(energy, S, idx, 1e-3)
+    expect = -g / (llg.MU0 * mu_s * mu_b)
+    got = np.array([H[i] for i in idx])
+    np.testing.assert_allclose(got, expect, rtol=1e-6, atol=1e-6 * np.abs(expect).max())
