@@ -1,19 +1,24 @@
 """Benchmark of the demagnetizing-field hot path on one MI355X.
 
-Workload (default): the thin-film LLG problem, 512 x 512 x 16 cells of 4 nm,
-Ms = 8e5 A/m, A = 1.3e-11 J/m, alpha = 0.02, RK4 with dt = 1e-13 s, seeded
-random unit m.  One step = one RK4 step = four H_d evaluations (x R2C, y FFT,
-z FFT + N^.M^ + z IFFT, y IFFT, x C2R) and four fused exchange + LLG stage
-updates, all in the library's HIP kernels, inputs resident in HBM.
+Workload (default): demag_field on the large film, 1024 x 1024 x 32 cells of
+4 nm (the largest single-GPU configuration), Ms = 8e5 A/m, seeded random unit
+M x Ms resident in HBM.  One step = one H_d evaluation of Eq. (1) as the
+zero-padded FFT convolution (x R2C, the y and z transforms, the symmetric
+tensor product and the inverse transforms), all in the library's HIP kernels.
 
-value = H_d evaluations x cells / wall time of the timed steps (Gcells/s),
-i.e. demag throughput inside the full RK4 step (the LLG kernels' time counts
-against it).  The roofline object describes the dominant kernel, timed live
-with HIP events around each of its launches in the timed region; its bytes are
-the algorithmic bytes of that kernel (inputs read once, outputs written once,
-zero padding never stored).
+value = cells / wall time per evaluation (Gcells/s) in FP32.  The roofline
+object describes the dominant kernel, timed live with HIP events around each of
+its launches on the launch stream; its bytes are the algorithmic bytes of that
+kernel (inputs read once, outputs written once, zero padding never stored), and
+its traffic is the HBM bytes per launch from stored rocprofv3 counter runs of
+the same kernels.  Extra keys: the BF16x3 MFMA form on the same film; the
+thin-film RK4 LLG block (512 x 512 x 16 cells, four H_d and four fused exchange
++ LLG stages per step, with the extrapolated-H_d and periodic variants); the
+small configuration's latency (32 x 32 x 4, eager and graph-replayed); a short
+serving sample; and the FP64 oracle timed on the host cores (cpu_baseline).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+       [--workload large_film|large_film_only|thin_film|atomistic|switching|field]
 """
 
 import argparse
@@ -31,6 +36,7 @@ KERNEL_SOURCES = ["paper_2308_08447_amd/csrc/" + f for f in (
     "stages_x.hip", "stages_y.hip", "stages_z.hip", "stages_xz.hip", "stage_common.h", "fft_lds.h",
     "mfma_dft.h", "engine.h", "dynamics.hip")]
 COUNTERS = "profiles/counters_thin_film_512x512x16.md"
+COUNTERS_LARGE = "profiles/counters_large_film_1024x1024x32.md"
 
 
 def kernel_sources_sha256():
@@ -42,11 +48,11 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def counter_traffic(stage):
+def counter_traffic(stage, counters=COUNTERS):
     """HBM bytes per launch of `stage` from the stored rocprofv3 counter runs
     (FETCH_SIZE x its copy-kernel calibration + WRITE_SIZE), or None when no
     measurement is stored or the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, COUNTERS)
+    path = os.path.join(ROOT, counters)
     if not os.path.exists(path):
         return None
     vals, sha = {}, None
@@ -96,12 +102,14 @@ def stage_bytes(n, form=5, pbc=(False, False, False)):
     }
 
 
-def cpu_baseline(n, cell, budget_s=20.0):
+def cpu_baseline(n, cell, budget_s=20.0, one_thread=True):
     """The FP64 oracle's FFT convolution on this host (set-up excluded)."""
     import workloads as W
     from oracle import demag as odemag
     workers = os.cpu_count() or 1
+    t_setup = time.perf_counter()
     op = odemag.DemagFFT(n, cell, workers=workers)
+    t_setup = time.perf_counter() - t_setup
     M = W.magnetisation(n, 0).astype(np.float64)
     op(M)  # warm-up
     times = []
@@ -112,11 +120,13 @@ def cpu_baseline(n, cell, budget_s=20.0):
         times.append(time.perf_counter() - t0)
     t = float(np.median(times))
     cells = n[0] * n[1] * n[2]
-    # one evaluation on a single thread, for a per-core figure
-    op1 = odemag.DemagFFT(n, cell, workers=1)
-    t0 = time.perf_counter()
-    op1(M)
-    t1 = time.perf_counter() - t0
+    del op
+    t1 = None
+    if one_thread:  # one evaluation on a single thread, for a per-core figure
+        op1 = odemag.DemagFFT(n, cell, workers=1)
+        t0 = time.perf_counter()
+        op1(M)
+        t1 = time.perf_counter() - t0
     model = None
     try:
         with open("/proc/cpuinfo") as f:
@@ -127,7 +137,8 @@ def cpu_baseline(n, cell, budget_s=20.0):
             "sample": f"{len(times)} FP64 H_d evaluations of the {n[0]}x{n[1]}x{n[2]} mesh "
                       f"(scipy rfftn/irfftn, workers={workers}; tensor set-up excluded), "
                       f"median {t:.3f} s each",
-            "one_thread_gcells_per_s": round(cells / t1 / 1e9, 6), "cpu_model": model}
+            "setup_s": round(t_setup, 2),
+            "one_thread_gcells_per_s": round(cells / t1 / 1e9, 6) if t1 else None, "cpu_model": model}
 
 
 def serve_run(pkg, reqs, rate, budget, max_active, flags):
@@ -225,6 +236,9 @@ def _stage_table(nbytes, stages, evals):
     return per_stage
 
 
+_LAST_VARIANTS = []  # tile variants the last _field_run's autotuning picked
+
+
 def _field_run(pkg, n, cell, flags, M, H, args, stream, label):
     """Autotuned demag_field on one mesh: per-stage event timing over args.steps
     evaluations, then the same number untimed.  Returns (seconds per
@@ -236,6 +250,7 @@ def _field_run(pkg, n, cell, flags, M, H, args, stream, label):
         pkg.demag_autotune(plan, stream)
         nch = pkg.demag_get_chunks(plan)
         form = pkg.demag_get_form(plan)
+        _LAST_VARIANTS[:] = [pkg.demag_get_variant(plan, st) for st in range(5)]
         print(f"{label}: timing", file=sys.stderr, flush=True)
         for _ in range(args.warmup):
             pkg.demag_field(plan, M, H, stream)
@@ -253,7 +268,7 @@ def _field_run(pkg, n, cell, flags, M, H, args, stream, label):
         t_field = (time.perf_counter() - t1) / args.steps
     finally:
         pkg.demag_destroy(plan)
-    return t_field, _stage_table(stage_bytes(n, form), stages, args.steps), nch
+    return t_field, _stage_table(stage_bytes(n, form), stages, args.steps), nch, form
 
 
 def large_film_bench(pkg, args):
@@ -272,9 +287,11 @@ def large_film_bench(pkg, args):
     b5 = sum(v for k, v in stage_bytes(n).items() if k != "llg")
     modes = {}
     for flags, name in ((0, "fp32"), (pkg.DEMAG_BF16X3_MFMA, "bf16x3_mfma")):
-        t_field, per_stage, nch = _field_run(pkg, n, cell, flags, M, H32 if flags == 0 else H,
-                                             args, stream, f"large film {name}")
+        t_field, per_stage, nch, form = _field_run(pkg, n, cell, flags, M, H32 if flags == 0 else H,
+                                                   args, stream, f"large film {name}")
         entry = {"Gcells_per_s": round(cells / t_field / 1e9, 3), "ms_per_eval": round(1e3 * t_field, 4),
+                 "form": "thin (x+z, y conv, z+x)" if form == 3 else "five-pass",
+                 "stage_variants": list(_LAST_VARIANTS),
                  "effective_hbm_frac": round(b5 / t_field / 1e9 / HBM_PEAK_GBS, 4),
                  "yz_chunks": nch, "stages": per_stage}
         if flags:
@@ -284,14 +301,23 @@ def large_film_bench(pkg, args):
     fp = modes["fp32"]
     per_stage = fp["stages"]
     dom = max(per_stage, key=lambda k: per_stage[k]["avg_us"] * per_stage[k]["launches"])
-    out = {"metric": "demag H_d evals: Gcells/s + % HBM roofline", "value": fp["Gcells_per_s"],
+    tr = [counter_traffic(k, COUNTERS_LARGE) for k in per_stage]
+    fp["counter_bytes_per_eval"] = (int(sum(t * per_stage[k]["launches"] / args.steps
+                                            for k, t in zip(per_stage, tr)))
+                                    if all(t is not None for t in tr) else None)
+    out = {"metric": "demag H_d evals: Gcells/s + % HBM roofline; serve p50/p99 latency",
+           "value": fp["Gcells_per_s"],
            "unit": "Gcells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": fp["ms_per_eval"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": cfg["name"], "mesh": list(n), "yz_chunks": fp["yz_chunks"]},
+           "config": {"workload": cfg["name"], "mesh": list(n), "cell_m": list(cell),
+                      "form": fp["form"], "yz_chunks": fp["yz_chunks"]},
            "roofline": {"bound": "hbm", "kernel": dom, "achieved": per_stage[dom]["GB_per_s"],
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(per_stage[dom]["GB_per_s"] / HBM_PEAK_GBS, 4), "traffic": None},
+                        "frac": round(per_stage[dom]["GB_per_s"] / HBM_PEAK_GBS, 4),
+                        "traffic": counter_traffic(dom, COUNTERS_LARGE),
+                        "bytes_per_launch": per_stage[dom]["bytes_per_launch"]},
+           "demag_field_bytes_b5": b5,
            "modes": modes}
     return out
 
@@ -307,9 +333,10 @@ def field_bench(pkg, args):
     stream = torch.cuda.current_stream()
     M = torch.from_numpy(W.magnetisation(n, 0)).cuda()
     H = torch.empty_like(M)
-    t_field, per_stage, nch = _field_run(pkg, n, W.CELL_4NM, 0, M, H, args, stream, f"field {n}")
+    t_field, per_stage, nch, form = _field_run(pkg, n, W.CELL_4NM, 0, M, H, args, stream, f"field {n}")
     return {"workload": "field", "mesh": list(n), "Gcells_per_s": round(cells / t_field / 1e9, 3),
-            "us_per_eval": round(1e6 * t_field, 1), "yz_chunks": nch, "stages": per_stage}
+            "us_per_eval": round(1e6 * t_field, 1), "form": form, "yz_chunks": nch,
+            "stage_variants": _LAST_VARIANTS, "stages": per_stage}
 
 
 def atomistic_bench(pkg, args):
@@ -332,9 +359,11 @@ def atomistic_bench(pkg, args):
     el = time.perf_counter() - t0
     pkg.atom_destroy(plan)
     norm_err = float((S.norm(dim=0) - 1).abs().max())
-    # Heun step bytes: 2 macro averages (12 B/spin each), predictor (read 12, write 24),
-    # corrector (read 36, write 12); neighbour re-reads come from cache
-    per_spin = 2 * 12 + 36 + 48
+    # algorithmic Heun step bytes: 2 macrocell averages (read S, read S_p: 12 B/spin
+    # each), predictor (read S, write S_p: 24), corrector (read S and S_p, write S:
+    # 36) = 84 B/spin; neighbour re-reads come from cache.  The kernels also store
+    # and re-read the predictor slope (24 B/spin more, 108 moved in all).
+    per_spin = 2 * 12 + 24 + 36
     ms = 1e3 * el / args.steps
     return {"metric": "atomistic spin-steps/s", "value": round(spins * args.steps / el / 1e9, 3),
             "unit": "Gspin-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -344,7 +373,8 @@ def atomistic_bench(pkg, args):
             "roofline": {"bound": "hbm", "kernel": "whole Heun step", "achieved":
                          round(per_spin * spins / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(per_spin * spins / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                         "traffic": None},
+                         "traffic": None, "bytes_per_spin": per_spin,
+                         "bytes_per_spin_moved_by_the_kernels": 108},
             "max_norm_error": norm_err}
 
 
@@ -414,70 +444,13 @@ def switching_bench(pkg, args):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-serve", action="store_true", help="skip the short serving sample")
-    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
-                    help="first run one plain device copy of MB megabytes (a known-size "
-                         "reference for hardware byte counters)")
-    ap.add_argument("--workload", default="thin_film",
-                    choices=("thin_film", "large_film", "atomistic", "switching", "field"),
-                    help="thin_film (default): 512x512x16 RK4 LLG; large_film: 1024x1024x32 "
-                         "demag_field; atomistic: 1024x1024x256 spins, Heun, 4^3 macrocells; "
-                         "switching: the 480x240x2 switching problem, 1 ns at 10-400 fs steps; "
-                         "field: demag_field alone on --mesh (for profiler runs)")
-    ap.add_argument("--mesh", default="512,512,16",
-                    help="field workload: cells nx,ny,nz (4 nm cubes)")
-    ap.add_argument("--variants", type=lambda s: [int(v) for v in s.split(",")], default=None,
-                    help="pin the tile variant of the five FFT stages (e.g. 1,1,1,1,1) instead "
-                         "of autotuning")
-    ap.add_argument("--chunks", type=int, default=0,
-                    help="pin the number of chunks the y/z stages run in instead of autotuning")
-    ap.add_argument("--serve-full", action="store_true",
-                    help="only the full serving workload: 256 requests x 1000 RK4 steps, "
-                         "Poisson loads 0.5/0.8/0.95 of the closed-loop throughput")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(use --gpus 1)", file=sys.stderr)
-        sys.exit(2)
-
+def thin_film_block(pkg, args):
+    """The thin-film LLG workload, 512 x 512 x 16 cells of 4 nm, RK4 dt = 1e-13 s:
+    timed RK4 steps (four H_d evaluations and four fused exchange + LLG stage
+    updates each) with per-stage event timing, the same steps with the
+    extrapolated H_d, the film periodic in x and y, and demag_field alone."""
     import torch
-    import paper_2308_08447_amd as pkg
     import workloads as W
-
-    if args.copy_probe:
-        src = torch.empty(args.copy_probe * 2**20 // 4, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    if args.serve_full:
-        res = serve_bench(pkg, 256, 1000, (0.5, 0.8, 0.95))
-        print(json.dumps({"metric": "serve p50/p99 latency", "data": "synthetic",
-                          "config": {"workload": "serving: 256 LLG relaxations, meshes "
-                                     "{32..512}^2 x {1,2,4,8}, 1000 RK4 steps each"},
-                          "serve": res}), flush=True)
-        return
-
-    if args.workload == "large_film":
-        print(json.dumps(large_film_bench(pkg, args)), flush=True)
-        return
-    if args.workload == "field":
-        print(json.dumps(field_bench(pkg, args)), flush=True)
-        return
-    if args.workload == "atomistic":
-        print(json.dumps(atomistic_bench(pkg, args)), flush=True)
-        return
-    if args.workload == "switching":
-        print(json.dumps(switching_bench(pkg, args)), flush=True)
-        return
-
     cfg = W.THIN_FILM
     n, cell = cfg["n"], cfg["cell"]
     cells = n[0] * n[1] * n[2]
@@ -565,30 +538,6 @@ def main():
                 "hd_us_per_eval": round(hd_p, 1),
                 "stages": per_stage_p}
 
-    # the small configuration (32x32x4): per-call latency, synchronous and
-    # pipelined; its 1.4 MB of traffic stays in the caches, so no roofline
-    n1 = W.DEMAG_SMALL["n"]
-    plan1 = pkg.demag_setup(n1 + W.DEMAG_SMALL["cell"], stream=stream)
-    M1 = torch.from_numpy(W.magnetisation(n1, 0)).to(dev)
-    H1 = torch.empty_like(M1)
-    for _ in range(20):
-        pkg.demag_field(plan1, M1, H1, stream)
-    torch.cuda.synchronize()
-    lat = []
-    for _ in range(200):
-        t0 = time.perf_counter()
-        pkg.demag_field(plan1, M1, H1, stream)
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - t0)
-    t0 = time.perf_counter()
-    for _ in range(1000):
-        pkg.demag_field(plan1, M1, H1, stream)
-    torch.cuda.synchronize()
-    small = {"mesh": list(n1), "sync_latency_us_median": round(1e6 * float(np.median(lat)), 1),
-             "pipelined_us_per_call": round(1e3 * (time.perf_counter() - t0), 2),
-             "note": "cache-resident and launch-bound: no HBM roofline"}
-    pkg.demag_destroy(plan1)
-
     # measured device-to-device copy bandwidth (read + write bytes / time)
     cp_src = torch.empty(256 * 2**20, dtype=torch.float32, device=dev)
     cp_dst = torch.empty_like(cp_src)
@@ -631,7 +580,7 @@ def main():
     counter_eval = int(sum(tr)) if tr and all(v is not None for v in tr) else None
 
     out = {
-        "metric": "demag H_d evals: Gcells/s + % HBM roofline; serve p50/p99 latency",
+        "metric": "demag H_d evals: Gcells/s + % HBM roofline (thin-film RK4 steps)",
         "value": round(value, 3),
         "unit": "Gcells/s",
         "n_gpus": 1,
@@ -660,16 +609,168 @@ def main():
         "demag_field_counter_bytes": counter_eval,
         "measured_copy_GB_per_s": round(copy_gbs, 1),
         "demag_field_frac_of_copy": round(b5 / t_field / 1e9 / copy_gbs, 4),
-        "small_config": small,
         "llg_cell_steps_per_s": round(cells * args.steps / elapsed, 1),
         "llg_extrapolated_hd": extrap,
         "pbc_xy": periodic,
     }
-    if not args.no_serve:
-        # short sample of the serving workload (64 requests x 100 RK4 steps)
-        out["serve"] = serve_bench(pkg, 64, 100, (0.8,))
+    return out
+
+
+def small_config_block(pkg):
+    """The small configuration, 32 x 32 x 4 cells: latency per demag_field call,
+    synchronous (call + synchronize) and pipelined (calls queued back to back),
+    each as the median over repeated windows, eagerly and by replaying the call
+    captured as a HIP graph.  Its 1.4 MB of traffic stays in the caches, so it
+    has no HBM roofline."""
+    import torch
+    import workloads as W
+    dev = torch.device("cuda:0")
+    n1 = W.DEMAG_SMALL["n"]
+    stream = torch.cuda.current_stream()
+    plan1 = pkg.demag_setup(n1 + W.DEMAG_SMALL["cell"], stream=stream)
+    M1 = torch.from_numpy(W.magnetisation(n1, 0)).to(dev)
+    H1 = torch.empty_like(M1)
+    try:
+        for _ in range(20):
+            pkg.demag_field(plan1, M1, H1, stream)
+        torch.cuda.synchronize()
+        H_eager = H1.clone()
+        # one call captured as a graph on a capture stream (kernel launches only)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            pkg.demag_field(plan1, M1, H1, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+
+        def windows(call, nwin=9, per=100):
+            sync, pipe = [], []
+            for _ in range(nwin):
+                lat = []
+                for _ in range(per):
+                    t0 = time.perf_counter()
+                    call()
+                    torch.cuda.synchronize()
+                    lat.append(time.perf_counter() - t0)
+                sync.append(float(np.median(lat)))
+                t0 = time.perf_counter()
+                for _ in range(per):
+                    call()
+                torch.cuda.synchronize()
+                pipe.append((time.perf_counter() - t0) / per)
+            return sync, pipe
+
+        s_e, p_e = windows(lambda: pkg.demag_field(plan1, M1, H1, stream))
+        H1.zero_()
+        s_g, p_g = windows(g.replay)
+        torch.cuda.synchronize()
+        graph_equal = bool(torch.equal(H1, H_eager))
+        del g
+    finally:
+        pkg.demag_destroy(plan1)
+    us = lambda v: round(1e6 * v, 1)
+    return {"mesh": list(n1),
+            "eager": {"sync_us_median": us(np.median(s_e)), "pipelined_us_median": us(np.median(p_e)),
+                      "pipelined_us_windows": [us(v) for v in p_e]},
+            "graph_replay": {"sync_us_median": us(np.median(s_g)), "pipelined_us_median": us(np.median(p_g)),
+                             "pipelined_us_windows": [us(v) for v in p_g],
+                             "bitwise_equal_to_eager": graph_equal},
+            "windows": "9 windows of 100 calls each",
+            "note": "cache-resident and launch-bound: no HBM roofline"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the short serving sample")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
+                    help="first run one plain device copy of MB megabytes (a known-size "
+                         "reference for hardware byte counters)")
+    ap.add_argument("--workload", default="large_film",
+                    choices=("large_film", "large_film_only", "thin_film", "atomistic", "switching", "field",
+                             "small"),
+                    help="large_film (default): 1024x1024x32 demag_field (FP32 and BF16x3 MFMA), plus "
+                         "the thin-film, small-configuration and serving blocks; large_film_only: "
+                         "the large film alone; thin_film: 512x512x16 RK4 LLG as the main line; "
+                         "atomistic: 1024x1024x256 spins, Heun, 4^3 macrocells; "
+                         "switching: the 480x240x2 switching problem, 1 ns at 10-400 fs steps; "
+                         "field: demag_field alone on --mesh (for profiler runs); small: the "
+                         "32x32x4 latency block alone")
+    ap.add_argument("--mesh", default="512,512,16",
+                    help="field workload: cells nx,ny,nz (4 nm cubes)")
+    ap.add_argument("--variants", type=lambda s: [int(v) for v in s.split(",")], default=None,
+                    help="pin the tile variant of the five FFT stages (e.g. 1,1,1,1,1) instead "
+                         "of autotuning")
+    ap.add_argument("--chunks", type=int, default=0,
+                    help="pin the number of chunks the y/z stages run in instead of autotuning")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="only the full serving workload: 256 requests x 1000 RK4 steps, "
+                         "Poisson loads 0.5/0.8/0.95 of the closed-loop throughput")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2308_08447_amd as pkg
+    import workloads as W
+
+    if args.copy_probe:
+        src = torch.empty(args.copy_probe * 2**20 // 4, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    if args.serve_full:
+        res = serve_bench(pkg, 256, 1000, (0.5, 0.8, 0.95))
+        print(json.dumps({"metric": "serve p50/p99 latency", "data": "synthetic",
+                          "config": {"workload": "serving: 256 LLG relaxations, meshes "
+                                     "{32..512}^2 x {1,2,4,8}, 1000 RK4 steps each"},
+                          "serve": res}), flush=True)
+        return
+
+    if args.workload == "field":
+        print(json.dumps(field_bench(pkg, args)), flush=True)
+        return
+    if args.workload == "small":
+        print(json.dumps(small_config_block(pkg)), flush=True)
+        return
+    if args.workload == "atomistic":
+        print(json.dumps(atomistic_bench(pkg, args)), flush=True)
+        return
+    if args.workload == "switching":
+        print(json.dumps(switching_bench(pkg, args)), flush=True)
+        return
+
+    if args.workload == "thin_film":
+        out = thin_film_block(pkg, args)
+        out["small_config"] = small_config_block(pkg)
+        if not args.no_serve:
+            out["serve"] = serve_bench(pkg, 64, 100, (0.8,))
+        if not args.no_cpu_baseline:
+            cfg = W.THIN_FILM
+            out["cpu_baseline"] = cpu_baseline(cfg["n"], cfg["cell"])
+        print(json.dumps(out), flush=True)
+        return
+
+    # default: demag_field on the large film (1024 x 1024 x 32, the largest
+    # single-GPU configuration), then the thin-film RK4 block, the small
+    # configuration's latency and a short serving sample as extra keys
+    out = large_film_bench(pkg, args)
+    if args.workload == "large_film":  # not for large_film_only
+        print("thin film: RK4 steps", file=sys.stderr, flush=True)
+        out["thin_film"] = thin_film_block(pkg, args)
+        print("small configuration: latency", file=sys.stderr, flush=True)
+        out["small_config"] = small_config_block(pkg)
+        if not args.no_serve:
+            out["serve"] = serve_bench(pkg, 64, 100, (0.8,))
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, cell)
+        cfg = W.LARGE_FILM
+        print("cpu baseline: FP64 oracle on the large film", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg["n"], cfg["cell"], budget_s=30.0, one_thread=False)
     print(json.dumps(out), flush=True)
 
 

@@ -277,12 +277,23 @@ int demag_timing_read(demag_plan* plan, double* total_ms, int32_t* launches);
 /*
  * Each FFT stage (DEMAG_STAGE_X_FWD .. DEMAG_STAGE_X_INV) has DEMAG_NVARIANTS
  * tile shapes (how many rows, lines or columns one workgroup transforms).  All
- * variants produce bit-identical results; they differ only in speed.
+ * variants of the five-pass stages produce bit-identical results; they differ
+ * only in speed.  In the thin-mesh form (DEMAG_FORM_THIN) the variant of
+ * X_FWD and X_INV sets the row pairs one workgroup transforms per round (8, 4
+ * or 2; 4, 2 or 1 at n_x = 1024), again bit-identical, and the variant of
+ * Z_CONV, where n_y >= 256, the y convolution's thread count (radix order) and
+ * columns per workgroup: variant 0 takes 128 threads (1024 = 16 8 8; n_y <= 512),
+ * 1 takes 256 threads (1024 = 16 16 4) and one column, 2 takes 256 threads and
+ * the two mirror planes kz, N_z - kz of a column, with the second column's
+ * loads in flight while the first is transformed.  Variants 1 and 2 give the
+ * same bits; variant 0 rounds differently.  Each is deterministic and within
+ * the 2e-5 contract.
  * demag_autotune times every variant of every stage on the plan's own buffers
  * (HIP events, 5 launches each; synchronises `stream`), keeps the fastest and
- * remembers the choice for later plans of the same mesh size in this process.
- * Plans made with a BF16 MFMA flag always run the middle tile shape (variant
- * 1, whatever is set); demag_autotune then tunes only the chunk count.
+ * remembers the choice for later plans of the same mesh size in this process
+ * (the serving engine's plans included).  Plans made with a BF16 MFMA flag
+ * always run the middle tile shape (variant 1, whatever is set);
+ * demag_autotune then tunes only the chunk count.
  */
 enum { DEMAG_NVARIANTS = 3 };
 int demag_autotune(demag_plan* plan, void* stream);
@@ -305,10 +316,11 @@ int demag_get_variant(demag_plan* plan, int32_t stage, int32_t* variant);
  *   DEMAG_FORM_FIVE_PASS   x R2C, y FFT, z convolution, y IFFT, x C2R
  *                          (stages X_FWD, Y_FWD, Z_CONV, Y_INV, X_INV);
  *   DEMAG_FORM_THIN        FP32 plans of thin meshes (32 <= n_x <= 1024,
- *                          16 <= n_y <= 512, n_z <= 16): x R2C with the z FFT
- *                          (timed as X_FWD), y FFT + tensor product + y IFFT
- *                          (timed as Z_CONV), z IFFT with the x C2R (X_INV).
- *                          The tile variants and the chunk count have no effect.
+ *                          16 <= n_y <= 1024, n_z <= 16, powers of two, open
+ *                          boundaries): x R2C with the z FFT (timed as X_FWD),
+ *                          y FFT + tensor product + y IFFT (timed as Z_CONV),
+ *                          z IFFT with the x C2R (X_INV).  The chunk count has
+ *                          no effect.
  * Both compute the same H (Eq. 1) to FP32 rounding.
  *   plan  in   plan;   form  out  one of the values below.
  * Errors: EINVAL (NULL argument).

@@ -259,7 +259,7 @@ int create_plan(const demag_mesh* mesh, uint32_t flags, hipStream_t s, demag_pla
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find({g.nx, g.ny, g.nz, p->mf});
-        if (it != g_tuned.end() && !p->xz && g.pbc == 0) {
+        if (it != g_tuned.end() && g.pbc == 0) {
             for (int i = 0; i < 5; ++i) p->variant[i] = it->second.variant[i];
             p->nch = it->second.nch;
         }
@@ -322,14 +322,15 @@ static int run_field_single(demag_plan* p, const float* M, float* H, float scale
     if (p->xz) {  // x + z forward, y convolution, z + x inverse
         {
             StageTimer t(p, DEMAG_STAGE_X_FWD, s);
-            if ((rc = launch_xz_forward(one(xzdesc(p, M, H, scale)), g.nx, g.nz, p->tw, s))) return rc;
+            if ((rc = launch_xz_forward(one(xzdesc(p, M, H, scale)), g.nx, g.nz, p->variant[0], p->tw, s)))
+                return rc;
         }
         {
             StageTimer t(p, DEMAG_STAGE_Z_CONV, s);
-            if ((rc = launch_yconv(one(ycdesc(p)), g.ny, g.Nz, p->tw, s))) return rc;
+            if ((rc = launch_yconv(one(ycdesc(p)), g.ny, g.Nz, p->variant[2], p->tw, s))) return rc;
         }
         StageTimer t(p, DEMAG_STAGE_X_INV, s);
-        return launch_xz_inverse(one(xzdesc(p, M, H, scale)), g.nx, g.nz, p->tw, s);
+        return launch_xz_inverse(one(xzdesc(p, M, H, scale)), g.nx, g.nz, p->variant[4], p->tw, s);
     }
     {
         StageTimer t(p, DEMAG_STAGE_X_FWD, s);
@@ -395,25 +396,37 @@ int run_fields(demag_plan* const* plans, const float* const* M, float* const* H,
     }
     if (!xitems.empty()) {
         const float2* tw = plans[xitems[0]]->tw;
-        auto by_xz = groups(xitems, [&](int i) { return plans[i]->g.nx * 64LL + plans[i]->g.nz; });
-        auto by_yc = groups(xitems, [&](int i) { return plans[i]->g.ny * 64LL + plans[i]->g.Nz; });
+        // a shared launch needs one shape and tile variant (the y convolution's
+        // variants round differently, so plans with different ones never share)
+        auto by_xz = groups(xitems, [&](int i) {
+            const demag_plan* p = plans[i];
+            return ((p->g.nx * 64LL + p->g.nz) * 4 + p->variant[0]) * 4 + p->variant[4];
+        });
+        auto by_yc = groups(xitems, [&](int i) {
+            return (plans[i]->g.ny * 128LL + plans[i]->g.Nz) * 4 + plans[i]->variant[2];
+        });
         for (auto& grp : by_xz) {
             XZBatch b;
             b.count = (int)grp.size();
             for (int r = 0; r < b.count; ++r) b.d[r] = xzdesc(plans[grp[r]], M[grp[r]], H[grp[r]], scale[grp[r]]);
-            if ((rc = launch_xz_forward(b, plans[grp[0]]->g.nx, plans[grp[0]]->g.nz, tw, s))) return rc;
+            if ((rc = launch_xz_forward(b, plans[grp[0]]->g.nx, plans[grp[0]]->g.nz, plans[grp[0]]->variant[0], tw,
+                                        s)))
+                return rc;
         }
         for (auto& grp : by_yc) {
             YCBatch b;
             b.count = (int)grp.size();
             for (int r = 0; r < b.count; ++r) b.d[r] = ycdesc(plans[grp[r]]);
-            if ((rc = launch_yconv(b, plans[grp[0]]->g.ny, plans[grp[0]]->g.Nz, tw, s))) return rc;
+            if ((rc = launch_yconv(b, plans[grp[0]]->g.ny, plans[grp[0]]->g.Nz, plans[grp[0]]->variant[2], tw, s)))
+                return rc;
         }
         for (auto& grp : by_xz) {
             XZBatch b;
             b.count = (int)grp.size();
             for (int r = 0; r < b.count; ++r) b.d[r] = xzdesc(plans[grp[r]], M[grp[r]], H[grp[r]], scale[grp[r]]);
-            if ((rc = launch_xz_inverse(b, plans[grp[0]]->g.nx, plans[grp[0]]->g.nz, tw, s))) return rc;
+            if ((rc = launch_xz_inverse(b, plans[grp[0]]->g.nx, plans[grp[0]]->g.nz, plans[grp[0]]->variant[4], tw,
+                                        s)))
+                return rc;
         }
     }
     if (items.empty()) return DEMAG_OK;
@@ -476,10 +489,11 @@ static LLGDesc llg_desc(const LLGStep& st, const float* ms, float* out, const fl
     const double mu0 = 4e-7 * 3.141592653589793238462643383279502884;
     const double cex = 2.0 * st.prm.A / (mu0 * st.prm.Ms);
     LLGDesc d;
+    float* rk = st.rk ? st.rk : p->rk;
     d.m = st.m;
     d.ms = ms;
-    d.Hd = Hd ? Hd : p->rk;
-    d.acc = p->rk + 3 * n3;
+    d.Hd = Hd ? Hd : rk;
+    d.acc = rk + 3 * n3;
     d.out = out;
     d.nx = g.nx;
     d.ny = g.ny;
@@ -566,22 +580,22 @@ int rk4_step_batch(const LLGStep* steps, int n, hipStream_t s) {
         return DEMAG_OK;
     }
     for (int i = 0; i < n; ++i)
-        if ((rc = ensure_rk(steps[i].plan))) return rc;
+        if (!steps[i].rk && (rc = ensure_rk(steps[i].plan))) return rc;
     std::vector<demag_plan*> plans(n);
     std::vector<const float*> ms(n);
     std::vector<float*> hd(n), outs(n);
     std::vector<float> scale(n);
     for (int i = 0; i < n; ++i) {
         plans[i] = steps[i].plan;
-        hd[i] = steps[i].plan->rk;
+        hd[i] = steps[i].rk ? steps[i].rk : steps[i].plan->rk;
         scale[i] = (float)steps[i].prm.Ms;
     }
     // stage inputs: m, A, B, A; stage outputs: A, B, A, m (the last one in place)
     for (int st = 0; st < 4; ++st) {
         for (int i = 0; i < n; ++i) {
             const size_t n3 = 3 * plans[i]->g.cells();
-            float* A = plans[i]->rk + n3;
-            float* B = plans[i]->rk + 2 * n3;
+            float* A = hd[i] + n3;
+            float* B = hd[i] + 2 * n3;
             const float* in[4] = {steps[i].m, A, B, A};
             float* out[4] = {A, B, A, steps[i].m};
             ms[i] = in[st];
@@ -834,8 +848,33 @@ int demag_autotune(demag_plan* plan, void* stream) {
         return DEMAG_OK;
     };
     // 1. tile variants, stage by stage, on the first chunk (the MFMA forms exist
-    //    in one tile shape only)
+    //    in one tile shape only).  Thin-mesh plans tune their three kernels:
+    //    row pairs per round of the two xz kernels and the thread count (radix
+    //    order) of the y convolution.
     rc = run_field_single(plan, M, H, 1.0f, s);
+    for (int st = 0; st < 5 && !rc && plan->xz; st += 2) {
+        const int LNY = 2 * g.ny;
+        const int nv = st == 2 ? (LNY >= 512 ? NVARIANTS : 1) : NVARIANTS;
+        if (nv < 2) continue;
+        double best = 1e30;
+        int best_v = plan->variant[st];
+        for (int v = 0; v < nv && !rc; ++v) {
+            auto fn = [&]() -> int {
+                switch (st) {
+                    case 0: return launch_xz_forward(one(xzdesc(plan, M, H, 1.0f)), g.nx, g.nz, v, plan->tw, s);
+                    case 2: return launch_yconv(one(ycdesc(plan)), g.ny, g.Nz, v, plan->tw, s);
+                    default: return launch_xz_inverse(one(xzdesc(plan, M, H, 1.0f)), g.nx, g.nz, v, plan->tw, s);
+                }
+            };
+            double ms = 0.0;
+            rc = time_it(fn, 5, &ms);
+            if (!rc && ms < best) {
+                best = ms;
+                best_v = v;
+            }
+        }
+        plan->variant[st] = best_v;
+    }
     const int per = (g.X1 + plan->nch - 1) / plan->nch;
     for (int st = 0; st < 5 && !rc && plan->mf == 0 && !plan->xz && g.pbc == 0; ++st) {
         if ((st == 1 || st == 3) && g.ny == 1) continue;

@@ -121,9 +121,11 @@ int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, h
 bool xz_supported(int nx, int ny, int nz);
 size_t xz_t_elems(int nx, int ny, int nz);
 int xz_groups(int X1);  // kx groups of T
-int launch_xz_forward(XZBatch b, int nx, int nz, const float2* tw, hipStream_t s);
-int launch_yconv(YCBatch b, int ny, int Nz, const float2* tw, hipStream_t s);
-int launch_xz_inverse(XZBatch b, int nx, int nz, const float2* tw, hipStream_t s);
+// variant: the tile variant of the stage (xz: row pairs per round; y conv: the
+// thread count and with it the radix order)
+int launch_xz_forward(XZBatch b, int nx, int nz, int variant, const float2* tw, hipStream_t s);
+int launch_yconv(YCBatch b, int ny, int Nz, int variant, const float2* tw, hipStream_t s);
+int launch_xz_inverse(XZBatch b, int nx, int nz, int variant, const float2* tw, hipStream_t s);
 // Twiddle table: exp(-2 pi i t/L), t < L, for every supported length L <= 4096
 // (2^k and F 2^k, F = 3, 5, 15), the table of length L at tw_offset(L).  The
 // regions are disjoint: 2^k at [2^k, 2^(k+1)), 3 2^k at 8192 + 4 2^k, 5 2^k at

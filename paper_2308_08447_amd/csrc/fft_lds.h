@@ -20,6 +20,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "mfma_dft.h"
 
 namespace dm {
@@ -33,6 +35,10 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// c + a b in four fused multiply-adds
+__device__ __forceinline__ float2 cmad(float2 a, float2 b, float2 c) {
+    return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y)));
+}
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 // multiply by -i (DIR = -1) or +i (DIR = +1)
 template <int DIR>
@@ -40,6 +46,8 @@ __device__ __forceinline__ float2 mul_i(float2 a) {
     if constexpr (DIR < 0) return make_float2(a.y, -a.x);
     else return make_float2(-a.y, a.x);
 }
+
+constexpr bool is_pow2_radix(int r) { return r >= 2 && r <= 16 && (r & (r - 1)) == 0; }
 
 // exp(DIR * 2 pi i k / 16), k < 8, as literal constants
 template <int DIR>
@@ -59,8 +67,126 @@ __device__ __forceinline__ float2 w16(int k) {
     return w;
 }
 
+// exp(DIR 2 pi i k / 16) for any k (reduced mod 16), exact constants
+template <int DIR>
+__device__ __forceinline__ float2 w16f(int k) {
+    k &= 15;
+    if (k < 8) return w16<DIR>(k);
+    float2 w = w16<DIR>(k - 8);
+    return make_float2(-w.x, -w.y);
+}
+
+// exp(DIR 2 pi i k / 32) for any k, exact constants (odd k from cos and sin of
+// pi/16 and 3 pi/16 by quadrant symmetry)
+template <int DIR>
+__device__ __forceinline__ float2 w32f(int k) {
+    k &= 31;
+    if ((k & 1) == 0) return w16f<DIR>(k >> 1);
+    constexpr float c1 = 0.98078528040323044f, s1 = 0.19509032201612826f;
+    constexpr float c3 = 0.83146961230254524f, s3 = 0.55557023301960222f;
+    const int q = k >> 3, j = k & 7;  // k = 8 q + j, angle = q pi/2 + j pi/16
+    float2 w = j == 1 ? make_float2(c1, s1) : j == 3 ? make_float2(c3, s3)
+             : j == 5 ? make_float2(s3, c3) : make_float2(s1, c1);
+    for (int t = 0; t < q; ++t) w = make_float2(-w.y, w.x);  // times i per quarter turn
+    if constexpr (DIR < 0) w.y = -w.y;
+    return w;
+}
+
+// Butterfly (a, b) -> (a + f b, a - f b) in six operations: four fused
+// multiply-adds form p = a + f b, and a - f b is taken as 2a - p.
+__device__ __forceinline__ void bfly(float2& a, float2& b, float2 f) {
+    const float px = fmaf(f.x, b.x, fmaf(-f.y, b.y, a.x));
+    const float py = fmaf(f.x, b.y, fmaf(f.y, b.x, a.y));
+    b = make_float2(fmaf(2.f, a.x, -px), fmaf(2.f, a.y, -py));
+    a = make_float2(px, py);
+}
+// The same with f = 1 and with f = DIR i (four operations each).
+__device__ __forceinline__ void bfly1(float2& a, float2& b) {
+    const float2 p = cadd(a, b);
+    b = csub(a, b);
+    a = p;
+}
+template <int DIR>
+__device__ __forceinline__ void bfly_i(float2& a, float2& b) {
+    const float2 t = mul_i<DIR>(b);
+    b = csub(a, t);
+    a = cadd(a, t);
+}
+
+// Twiddle sources of the power-of-two DFT below.  The transform of size R
+// (radix-2 decimation in time) combines at depth d sub-transforms of size
+// S = R / 2^d with factors g_d omega_S^m (m < S/2, omega_S = exp(DIR 2 pi i/S)):
+//   TwNone    g_d = 1: the plain DFT of v;
+//   TwHalf    v[r] is weighted by omega_{2R}^r, so the factor is the exact
+//             constant omega_{2S}^{2m+1} (the odd outputs of a length-2R DFT
+//             whose upper R inputs are zero);
+//   TwRun     v[r] is weighted by w^r for a run-time w, g_d = w^(2^d) taken
+//             from p[d] (each a table entry, so no power is formed by repeated
+//             products).
+struct TwNone {};
+struct TwHalf {};
+struct TwRun {
+    float2 p[4];
+};
+
+// Factor of combination m at depth D for a transform of size R (S = R >> D),
+// applied as a butterfly; the trivial ones (1 and DIR i) skip the products.
+template <int R, int D, int DIR, class TWS>
+__device__ __forceinline__ void combine(float2& a, float2& b, int m, const TWS& tws) {
+    constexpr int S = R >> D;
+    if constexpr (std::is_same<TWS, TwNone>::value) {
+        if (m == 0) bfly1(a, b);
+        else if (4 * m == S) bfly_i<DIR>(a, b);
+        else bfly(a, b, w16f<DIR>(m * (16 / S)));
+    } else if constexpr (std::is_same<TWS, TwHalf>::value) {
+        // omega_{2S}^{2m+1} = w32f((2m+1) 16/S); S = 2 gives omega_4 = DIR i
+        if (S == 2) bfly_i<DIR>(a, b);
+        else bfly(a, b, w32f<DIR>((2 * m + 1) * (16 / S)));
+    } else {
+        const float2 g = tws.p[D];
+        if (m == 0) {
+            bfly(a, b, g);
+        } else if (4 * m == S) {
+            bfly(a, b, mul_i<DIR>(g));
+        } else if (4 * m < S) {
+            bfly(a, b, cmul(g, w16f<DIR>(m * (16 / S))));
+        } else {  // omega_S^m = DIR i omega_S^(m - S/4): the same product, rotated
+            bfly(a, b, mul_i<DIR>(cmul(g, w16f<DIR>((m - S / 4) * (16 / S)))));
+        }
+    }
+}
+
+template <int R, int D, int DIR, class TWS>
+__device__ __forceinline__ void dft2k_rec(float2* v, const TWS& tws) {
+    constexpr int S = R >> D;
+    if constexpr (S >= 2) {
+        float2 e[S / 2], o[S / 2];
+#pragma unroll
+        for (int i = 0; i < S / 2; ++i) {
+            e[i] = v[2 * i];
+            o[i] = v[2 * i + 1];
+        }
+        dft2k_rec<R, D + 1, DIR>(e, tws);
+        dft2k_rec<R, D + 1, DIR>(o, tws);
+#pragma unroll
+        for (int m = 0; m < S / 2; ++m) {
+            combine<R, D, DIR>(e[m], o[m], m, tws);
+            v[m] = e[m];
+            v[m + S / 2] = o[m];
+        }
+    }
+}
+
+// DFT of size R (a power of two <= 16) of v[r] g^r with g given by the twiddle
+// source (see above), natural order in and out.
+template <int R, int DIR, class TWS>
+__device__ __forceinline__ void dft2k(float2* v, const TWS& tws) {
+    static_assert(R >= 1 && R <= 16 && (R & (R - 1)) == 0, "power of two <= 16");
+    dft2k_rec<R, 0, DIR>(v, tws);
+}
+
 // In-register DFT of size R: 3 and 5 by the symmetric-pair formulas, powers of
-// two <= 16 by radix-2 decimation in time.
+// two <= 16 by radix-2 decimation in time with multiply-add butterflies.
 template <int R, int DIR>
 __device__ __forceinline__ void dft(float2* v) {
     if constexpr (R == 1) {
@@ -90,28 +216,8 @@ __device__ __forceinline__ void dft(float2* v) {
         v[4] = csub(r1, i1);
         v[2] = cadd(r2, i2);
         v[3] = csub(r2, i2);
-    } else if constexpr (R == 2) {
-        float2 a = v[0], b = v[1];
-        v[0] = cadd(a, b);
-        v[1] = csub(a, b);
     } else {
-        float2 e[R / 2], o[R / 2];
-#pragma unroll
-        for (int i = 0; i < R / 2; ++i) {
-            e[i] = v[2 * i];
-            o[i] = v[2 * i + 1];
-        }
-        dft<R / 2, DIR>(e);
-        dft<R / 2, DIR>(o);
-#pragma unroll
-        for (int k = 0; k < R / 2; ++k) {
-            float2 t;
-            if (k == 0) t = o[0];
-            else if (4 * k == R) t = mul_i<DIR>(o[k]);
-            else t = cmul(w16<DIR>(k * (16 / R)), o[k]);
-            v[k] = cadd(e[k], t);
-            v[k + R / 2] = csub(e[k], t);
-        }
+        dft2k<R, DIR>(v, TwNone{});
     }
 }
 
@@ -134,15 +240,40 @@ __device__ __forceinline__ void dft_half_in(float2* v) {
 #pragma unroll
         for (int r = 0; r < R / 2; ++r) {
             e[r] = v[r];
-            o[r] = rot16<DIR>(r * (16 / R), v[r]);
+            o[r] = v[r];
         }
-        dft<R / 2, DIR>(e);
-        dft<R / 2, DIR>(o);
+        dft2k<R / 2, DIR>(e, TwNone{});
+        dft2k<R / 2, DIR>(o, TwHalf{});
 #pragma unroll
         for (int m = 0; m < R / 2; ++m) {
             v[2 * m] = e[m];
             v[2 * m + 1] = o[m];
         }
+    }
+}
+
+// Twiddled DFT of a Stockham pass: the DFT of v[r] w^r, w = tw[s] (conjugated
+// for the inverse, DIR > 0).  Powers of two take w^(2^d) = tw[2^d s] as table
+// entries; other radices multiply every input.
+template <int R, int DIR, class TW>
+__device__ __forceinline__ void dft_twiddled(float2* v, const TW& tw, int s) {
+    if constexpr (is_pow2_radix(R)) {
+        TwRun t;
+#pragma unroll
+        for (int d = 0; (1 << d) < R; ++d) {
+            float2 w = tw[s << d];
+            if constexpr (DIR > 0) w.y = -w.y;
+            t.p[d] = w;
+        }
+        dft2k<R, DIR>(v, t);
+    } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            float2 w = tw[s * r];
+            if constexpr (DIR > 0) w.y = -w.y;
+            v[r] = cmul(v[r], w);
+        }
+        dft<R, DIR>(v);
     }
 }
 
@@ -264,16 +395,8 @@ __device__ __forceinline__ void stockham_pass(float2* buf, TW tw) {
             const float2* src = buf + Addr::idx(line, j);
 #pragma unroll
             for (int r = 0; r < R; ++r) v[q][r] = src[Addr::template at<P2>(j, r * NB)];
-            if constexpr (NS > 1) {
-                int k = j % NS;
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    float2 w = tw[k * r * (L / (NS * R))];
-                    if constexpr (DIR > 0) w.y = -w.y;
-                    v[q][r] = cmul(v[q][r], w);
-                }
-            }
-            dft<R, DIR>(v[q]);
+            if constexpr (NS > 1) dft_twiddled<R, DIR>(v[q], tw, (j % NS) * (L / (NS * R)));
+            else dft<R, DIR>(v[q]);
         }
     }
     __syncthreads();
@@ -380,13 +503,7 @@ __device__ __forceinline__ void last_pass(float2* buf, TW tw, Sink& sink) {
         if (TOT % NT == 0 || b < TOT) {
             int line, j;
             Addr::template split<NB>(b, line, j);
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                float2 w = tw[j * r];
-                if constexpr (DIR > 0) w.y = -w.y;
-                v[q][r] = cmul(v[q][r], w);
-            }
-            dft<R, DIR>(v[q]);
+            dft_twiddled<R, DIR>(v[q], tw, j);
             constexpr int ROUT = HALF_OUT ? R / 2 : R;
 #pragma unroll
             for (int r = 0; r < ROUT; ++r) sink(line, j + r * NB, v[q][r]);

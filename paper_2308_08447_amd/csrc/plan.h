@@ -91,6 +91,7 @@ struct LLGStep {            // one mesh in a batched RK4 step
     float* m;
     llg_params prm;
     double dt;
+    float* rk = nullptr;    // RK4 buffers (12 N floats); nullptr: the plan's own
 };
 // One classic RK4 step for every mesh in `steps` (batched launches).
 int rk4_step_batch(const LLGStep* steps, int n, hipStream_t s);

@@ -1,16 +1,25 @@
 // serve.hip -- continuous batching of independent LLG simulations on one GPU.
 //
-// A worker thread owns a HIP stream and loops:
-//   1. admit queued requests while their device memory fits the budget (the
-//      transformed tensor of a mesh is counted once for all active requests of
-//      that mesh and shared through the process-wide cache);
-//   2. advance every active request by q RK4 steps, q = the fewest steps any
-//      active request still needs (at most QUANTUM), with shared launches: one
-//      launch per FFT stage and transform length, one LLG launch per 16 meshes.
-//      With SERVE_GRAPHS the launches of one step are captured into a HIP graph
-//      once per distinct active set and replayed;
-//   3. retire finished requests (copy m to host, free their memory), which lets
-//      waiting requests in at the next iteration.
+// Two threads with a HIP stream each:
+//   worker       loops: (1) admits queued requests while their device memory
+//                fits the budget (the transformed tensor of a mesh is counted
+//                once for all resident requests of that mesh and shared through
+//                the process-wide cache), scanning the queue in arrival order:
+//                a request that fits may pass one that does not, until the one
+//                at the head has been passed MAX_BYPASS times, after which the
+//                freed memory is held for it; (2) moves requests whose set-up
+//                is done into the active set; (3) advances every active request
+//                by q RK4 steps, q = the fewest steps any active request still
+//                needs (at most QUANTUM; prepared requests join in groups, see
+//                MERGE_COUNT), with shared launches: one launch per
+//                FFT stage and transform length, one LLG launch per 16 meshes;
+//                with SERVE_GRAPHS the launches of one step are captured into a
+//                HIP graph once per distinct active set and replayed; (4)
+//                retires finished requests (copy m to host, free their memory).
+//   preparation  creates the plans of admitted requests (a new mesh's FP64
+//                tensor set-up included) and uploads m0 on its own stream, so
+//                that this work overlaps the worker's steps instead of stalling
+//                them.
 // Each request's arithmetic does not depend on which other requests share its
 // launches, so a result is bit-identical to running the request alone.
 #include <algorithm>
@@ -28,6 +37,9 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 constexpr int QUANTUM = 16;
+constexpr int MAX_BYPASS = 16;  // admissions that may pass the request at the head
+constexpr int MERGE_COUNT = 16;  // ready requests that join the active set at once
+constexpr auto MERGE_WAIT = std::chrono::milliseconds(20);
 
 struct Request {
     uint64_t id = 0;
@@ -37,10 +49,12 @@ struct Request {
     int nsteps = 0;
     std::vector<float> host;  // m0 on submission, the result on completion
     int steps_done = 0;
-    enum { QUEUED, ACTIVE, DONE } state = QUEUED;
+    enum { QUEUED, PREPARING, READY, ACTIVE, DONE } state = QUEUED;
+    size_t need = 0;          // budget reserved at admission
+    int bypassed = 0;         // admissions that passed this request while it waited
     int status = DEMAG_OK;
     std::string error;
-    Clock::time_point t_submit, t_done;
+    Clock::time_point t_submit, t_done, t_ready;
     demag_plan* plan = nullptr;
     float* m = nullptr;
     size_t bytes = 0;         // workspace + RK4 + m
@@ -58,11 +72,15 @@ struct demag_server {
     uint32_t flags = 0;
     int device = 0;
     hipStream_t stream = nullptr;
-    std::thread worker;
+    hipStream_t prep_stream = nullptr;  // plan set-up and m0 uploads (default priority)
+    std::thread worker, prep;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_done, cv_prep;
     std::deque<Request*> queue;
+    std::deque<Request*> preparing;      // admitted, set-up pending
+    std::vector<Request*> ready;         // set up, not yet in the active set
     std::vector<Request*> active;
+    int admitted = 0;                    // preparing + ready + active
     std::unordered_map<uint64_t, Request*> reqs;
     std::map<ShapeKey, int> active_shapes;  // active requests per mesh (tensor held once)
     uint64_t next_id = 1;
@@ -114,48 +132,77 @@ void finish(demag_server* s, Request* r, int status, const std::string& err) {
     }
 }
 
-// Admits queued requests (lock held while deciding; device set-up outside).
+// Admits queued requests (worker thread): reserves their budget and hands them
+// to the preparation thread.  Requests are taken in arrival order; one that
+// does not fit yet may be passed by later ones that do, until it has been
+// passed MAX_BYPASS times.
 void admit(demag_server* s) {
-    for (;;) {
-        Request* r = nullptr;
-        size_t need = 0;
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            if (s->queue.empty() || (int)s->active.size() >= s->max_active) return;
-            r = s->queue.front();
-            need = admission_bytes(s, r);
-            if (need > s->budget) {  // can never fit
-                s->queue.pop_front();
-                finish(s, r, DEMAG_ENOMEM, "request needs more device memory than the budget");
-                s->cv_done.notify_all();
-                continue;
-            }
-            if (s->used + need > s->budget) return;  // wait for memory to free up
-            s->queue.pop_front();
-            s->used += need;
-            s->active_shapes[shape_key(r->mesh)]++;
-            if (s->used > s->st.peak_bytes) s->st.peak_bytes = s->used;
-        }
-        int rc = dm::create_plan(&r->mesh, DEMAG_FP32, s->stream, &r->plan);
-        if (!rc) rc = dm::ensure_rk(r->plan);
-        if (!rc) rc = dm::dev_alloc((void**)&r->m, r->host.size() * sizeof(float), "request m");
-        if (!rc && hipMemcpyAsync(r->m, r->host.data(), r->host.size() * sizeof(float),
-                                  hipMemcpyHostToDevice, s->stream) != hipSuccess)
-            rc = dm::fail(DEMAG_EHIP, "copy of m0 to the device failed");
-        if (!rc && hipStreamSynchronize(s->stream) != hipSuccess)
-            rc = dm::fail(DEMAG_EHIP, "stream synchronisation failed");
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (rc) {
-            std::string err = demag_last_error();
-            release(s, r);
-            s->used -= need;
-            s->active_shapes[shape_key(r->mesh)]--;
-            finish(s, r, rc, err);
+    std::lock_guard<std::mutex> lk(s->mu);
+    bool handed = false;
+    for (auto it = s->queue.begin(); it != s->queue.end() && s->admitted < s->max_active;) {
+        Request* r = *it;
+        const size_t need = admission_bytes(s, r);
+        if (need > s->budget) {  // can never fit
+            it = s->queue.erase(it);
+            finish(s, r, DEMAG_ENOMEM, "request needs more device memory than the budget");
             s->cv_done.notify_all();
             continue;
         }
-        r->state = Request::ACTIVE;
-        s->active.push_back(r);
+        if (s->used + need > s->budget) {
+            if (r->bypassed >= MAX_BYPASS) break;  // hold the memory that frees up for it
+            ++it;
+            continue;
+        }
+        for (auto jt = s->queue.begin(); jt != it; ++jt) (*jt)->bypassed++;
+        it = s->queue.erase(it);
+        r->need = need;
+        s->used += need;
+        s->active_shapes[shape_key(r->mesh)]++;
+        if (s->used > s->st.peak_bytes) s->st.peak_bytes = s->used;
+        r->state = Request::PREPARING;
+        s->preparing.push_back(r);
+        s->admitted++;
+        handed = true;
+    }
+    if (handed) s->cv_prep.notify_one();
+}
+
+// Preparation thread: plan (tensor set-up on first use of a mesh), RK4
+// buffers, m0 upload, on its own stream; the request is then ready to join the
+// active set.
+void prep_main(demag_server* s) {
+    (void)hipSetDevice(s->device);
+    for (;;) {
+        Request* r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_prep.wait(lk, [&] { return s->stop || !s->preparing.empty(); });
+            if (s->stop) return;
+            r = s->preparing.front();
+            s->preparing.pop_front();
+        }
+        int rc = dm::create_plan(&r->mesh, DEMAG_FP32, s->prep_stream, &r->plan);
+        if (!rc) rc = dm::ensure_rk(r->plan);
+        if (!rc) rc = dm::dev_alloc((void**)&r->m, r->host.size() * sizeof(float), "request m");
+        if (!rc && hipMemcpyAsync(r->m, r->host.data(), r->host.size() * sizeof(float),
+                                  hipMemcpyHostToDevice, s->prep_stream) != hipSuccess)
+            rc = dm::fail(DEMAG_EHIP, "copy of m0 to the device failed");
+        if (!rc && hipStreamSynchronize(s->prep_stream) != hipSuccess)
+            rc = dm::fail(DEMAG_EHIP, "stream synchronisation failed");
+        std::string err = rc ? std::string(demag_last_error()) : std::string();
+        if (rc) release(s, r);
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (rc) {
+            s->used -= admission_bytes_release(s, r);
+            s->admitted--;
+            finish(s, r, rc, err);
+            s->cv_done.notify_all();
+        } else {
+            r->state = Request::READY;
+            r->t_ready = Clock::now();
+            s->ready.push_back(r);
+        }
+        s->cv_work.notify_one();
     }
 }
 
@@ -234,6 +281,7 @@ void iterate(demag_server* s) {
         release(s, r);
         std::lock_guard<std::mutex> lk(s->mu);
         s->used -= admission_bytes_release(s, r);
+        s->admitted--;
         finish(s, r, frc, ferr);
     }
     std::lock_guard<std::mutex> lk(s->mu);
@@ -251,14 +299,34 @@ void worker_main(demag_server* s) {
     (void)hipSetDevice(s->device);
     for (;;) {
         {
+            // sleep while nothing can advance: no active request, nothing ready,
+            // and the queue empty or blocked until memory frees up
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
+            s->cv_work.wait(lk, [&] {
+                return s->stop || !s->active.empty() || !s->ready.empty() ||
+                       (!s->queue.empty() && s->admitted < s->max_active && s->preparing.empty());
+            });
             if (s->stop) return;
         }
         admit(s);
         bool any;
         {
+            // Ready requests join the active set together, so that a burst of
+            // arrivals changes the captured step once, not once per request:
+            // when nothing is active, when nothing else is being prepared, when
+            // MERGE_COUNT are waiting or the oldest has waited MERGE_WAIT.
             std::lock_guard<std::mutex> lk(s->mu);
+            const bool merge = !s->ready.empty() &&
+                               (s->active.empty() || s->preparing.empty() ||
+                                (int)s->ready.size() >= MERGE_COUNT ||
+                                Clock::now() - s->ready.front()->t_ready >= MERGE_WAIT);
+            if (merge) {
+                for (Request* r : s->ready) {
+                    r->state = Request::ACTIVE;
+                    s->active.push_back(r);
+                }
+                s->ready.clear();
+            }
             any = !s->active.empty();
         }
         if (any) iterate(s);
@@ -285,7 +353,13 @@ int serve_open(size_t hbm_budget_bytes, int32_t max_active, uint32_t flags, dema
         delete s;
         return dm::fail(DEMAG_EHIP, "hipStreamCreate failed");
     }
+    if (hipStreamCreateWithFlags(&s->prep_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(s->stream);
+        delete s;
+        return dm::fail(DEMAG_EHIP, "hipStreamCreate failed");
+    }
     s->worker = std::thread(worker_main, s);
+    s->prep = std::thread(prep_main, s);
     *out = s;
     return DEMAG_OK;
 }
@@ -366,14 +440,18 @@ int serve_close(demag_server* s) {
     }
     s->cv_work.notify_all();
     s->cv_done.notify_all();
+    s->cv_prep.notify_all();
     if (s->worker.joinable()) s->worker.join();
+    if (s->prep.joinable()) s->prep.join();
     (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->prep_stream);
     for (auto& kv : s->reqs) {
         release(s, kv.second);
         delete kv.second;
     }
     if (s->exec) (void)hipGraphExecDestroy(s->exec);
     (void)hipStreamDestroy(s->stream);
+    (void)hipStreamDestroy(s->prep_stream);
     delete s;
     return DEMAG_OK;
 }

@@ -166,7 +166,7 @@ __global__ __launch_bounds__(NT) void x_inverse_kernel(const XBatch b,
     }
     __syncthreads();
     auto combine = [&](int p, int t, float2 io) {
-        float2 zz = cadd(ie[p * LS + lpad(t)], cmul(cconj(tw2L[t]), io));
+        float2 zz = cmad(cconj(tw2L[t]), io, ie[p * LS + lpad(t)]);
         if (2 * p < rows) dst[(size_t)(2 * p) * L + t] = zz.x;
         if (2 * p + 1 < rows) dst[(size_t)(2 * p + 1) * L + t] = zz.y;
     };

@@ -1,5 +1,5 @@
 // stages_xz.hip -- the three-kernel form of the convolution for thin meshes
-// (n_z <= 16, n_y <= 512, 32 <= n_x <= 1024).
+// (n_z <= 16, 16 <= n_y <= 1024, 32 <= n_x <= 1024).
 //
 // The z transform moves into the x kernels, where the n_z rows of one (c, y)
 // line of cells are all in hand:
@@ -25,7 +25,7 @@ constexpr int TKB = 4;  // kx columns per T group
 
 template <int L>
 struct XZShape {
-    static constexpr int NTA = L / 2 < 64 ? 64 : L / 2;   // thread t owns kx = 2t, 2t+1
+    static constexpr int NTA = L < 64 ? 64 : L;           // thread t owns column kx = t
     static constexpr int L2 = 2 * L;                      // padded x length
     static constexpr int LS = lpad_c(L2) + 1;
 };
@@ -34,11 +34,18 @@ template <int NZS>
 struct ZShape {
     static constexpr int NZ = NZS > 1 ? 2 * NZS : 1;      // padded z length
     static constexpr int NPAIR = NZS > 1 ? NZS / 2 : 1;   // packed row pairs
+    static constexpr int H = NZS > 1 ? NZS / 2 : 1;       // length of the z sub-transforms
 };
 
-template <int L, int NZS>
+// Row pairs transformed together per round (tile variant V = 0, 1, 2): up to
+// 8, 4 or 2 pairs (4, 2, 1 at 2L = 2048, where the 1024-thread block also holds
+// a 32-row column in registers).  More pairs give every thread a butterfly in
+// the radix-16 passes; fewer take less LDS, so more blocks share a compute
+// unit.  The per-line arithmetic is the same, so every variant gives the same
+// bits.
+template <int L, int NZS, int V>
 struct XZRounds {
-    static constexpr int CAP = 2048 / L > 0 ? 2048 / L : 1;
+    static constexpr int CAP = (L >= 1024 ? 4 : 8) >> V;
     static constexpr int NPR = ZShape<NZS>::NPAIR < CAP ? ZShape<NZS>::NPAIR : CAP;  // pairs per round
     static constexpr int NR = ZShape<NZS>::NPAIR / NPR;
 };
@@ -52,17 +59,103 @@ __device__ __forceinline__ size_t t_index(int c, int kz, int NZ, int G, int ny, 
     return ((((size_t)c * NZ + kz) * G + kx / TKB) * ny + y) * TKB + kx % TKB;
 }
 
+// ---- z transforms of one kx column in the registers of one thread
+// Padded length NZ = 2 NZS, inputs z >= NZS zero.  With H = NZS / 2, writing
+// z = z' + H p (p = 0, 1; p = 2, 3 fall in the zero half) and kz = 4 q + r,
+//   Y[4q + r] = sum_{z' < H} W_H^{z' q} W_NZ^{r z'} c_r[z'],
+//   c_r[z'] = x[z'] + (W_4)^r x[z' + H]                       (W_4 = -i),
+// so each class r of outputs is the H-point DFT of c_r weighted by W_NZ^{r z'}:
+// plain for r = 0, the exact half-step weights for r = 2 (W_NZ^2 = W_{2H}), and
+// table powers W_NZ^{r 2^d} for r = 1, 3.  Classes are produced one at a time,
+// so a thread holds its column plus one class.
+template <int NZS, class Out>
+__device__ __forceinline__ void z_forward(const float2* x, const float2* __restrict__ twz, Out out) {
+    using Z = ZShape<NZS>;
+    if constexpr (NZS == 1) {
+        out(0, x[0]);
+    } else {
+        constexpr int H = Z::H;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float2 v[H];
+#pragma unroll
+            for (int z = 0; z < H; ++z) {
+                const float2 u = x[z + H];
+                const float2 t = r == 0 ? u : r == 1 ? mul_i<-1>(u) : r == 2 ? make_float2(-u.x, -u.y)
+                                                                                : mul_i<+1>(u);
+                v[z] = cadd(x[z], t);
+            }
+            if (r == 0) {
+                dft2k<H, -1>(v, TwNone{});
+            } else if (r == 2) {
+                dft2k<H, -1>(v, TwHalf{});
+            } else {
+                TwRun w;
+#pragma unroll
+                for (int d = 0; (1 << d) < H; ++d) w.p[d] = twz[r << d];
+                dft2k<H, -1>(v, w);
+            }
+#pragma unroll
+            for (int q = 0; q < H; ++q) out(4 * q + r, v[q]);
+        }
+    }
+}
+
+// Truncated inverse of the above: h[z] = sum_kz Y[kz] W_NZ^{-kz z}, z < NZS.
+// With the same split, G_r[z'] = sum_q Y[4q + r] W_H^{-q z'} (an H-point
+// inverse DFT of class r), t_r = W_NZ^{-r z'} G_r[z'], and
+//   h[z'] = sum_r t_r[z'],   h[z' + H] = sum_r (i)^r t_r[z'].
+// in(kz) returns Y[kz]; classes are read one at a time.
+template <int NZS, class In>
+__device__ __forceinline__ void z_inverse(float2* h, const float2* __restrict__ twz, In in) {
+    using Z = ZShape<NZS>;
+    if constexpr (NZS == 1) {
+        h[0] = in(0);
+    } else {
+        constexpr int H = Z::H;
+        // class 0 sets h; classes 1..3 add to it (a rolled loop: the class
+        // index only selects table entries and the rotation by i^r, and one
+        // class of loads in flight keeps the registers to h plus one class)
+#pragma unroll
+        for (int q = 0; q < H; ++q) h[q] = in(4 * q);
+        dft2k<H, +1>(h, TwNone{});
+#pragma unroll
+        for (int z = 0; z < H; ++z) h[z + H] = h[z];
+#pragma unroll 1
+        for (int r = 1; r < 4; ++r) {
+            float2 g[H];
+#pragma unroll
+            for (int q = 0; q < H; ++q) g[q] = in(4 * q + r);
+            dft2k<H, +1>(g, TwNone{});
+            // rotation of the upper half by i^r: (re, im) -> (sr re - si im, si re + sr im)
+            const float sr = r == 2 ? -1.f : 0.f, si = r == 1 ? 1.f : (r == 3 ? -1.f : 0.f);
+#pragma unroll
+            for (int z = 0; z < H; ++z) {
+                const float2 t = z == 0 ? g[0] : cmul(cconj(twz[r * z]), g[z]);
+                h[z] = cadd(h[z], t);
+                h[z + H] = cadd(h[z + H], make_float2(fmaf(sr, t.x, -(si * t.y)), fmaf(si, t.x, sr * t.y)));
+            }
+        }
+    }
+}
+
 // ============================================================================ xz forward
-template <int L, int NZS>
+// One block: component c, row y, all nz rows.  Rows are packed in pairs
+// (z, z+1) as a + i b, NPR pairs per round go through the length-2L transform
+// in LDS (upper half zero), and thread t takes column kx = t of every row out of
+// the Hermitian pair; after the last round it runs the z transform of its
+// column in registers and stores the Nz values.  The real Nyquist column
+// kx = L is transformed by a direct DFT.
+template <int L, int NZS, int V>
 __global__ __launch_bounds__(XZShape<L>::NTA) void xz_forward_kernel(const XZBatch b,
                                                                    const float2* __restrict__ tw_all) {
     using S = XZShape<L>;
     using Z = ZShape<NZS>;
-    using RR = XZRounds<L, NZS>;
+    using RR = XZRounds<L, NZS, V>;
     constexpr int NTA = S::NTA, L2 = S::L2, LS = S::LS, NZ = Z::NZ, NPR = RR::NPR;
     __shared__ float2 buf[NPR * LS];
     __shared__ float2 tw2[L2];
-    __shared__ float2 nyq[2 * Z::NPAIR];
+    __shared__ float nyq[NZS];
     stage_table_n<NTA>(tw2, tw_all + tw_offset(L2), L2);
     const int t = threadIdx.x;
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
@@ -74,9 +167,9 @@ __global__ __launch_bounds__(XZShape<L>::NTA) void xz_forward_kernel(const XZBat
     const int G = (L + 1 + TKB - 1) / TKB;
     const float* __restrict__ rows = b.d[item].M + ((size_t)c * NZS * ny + y) * L;  // row z at + z ny L
     float2* __restrict__ T = b.d[item].T;
-    const bool owner = t < L / 2;
+    const bool owner = t < L;
 
-    float2 col[2][NZS];  // x spectra of the two owned kx columns, rows 0..nz-1
+    float2 col[NZS];  // x spectrum of column kx = t, rows 0..nz-1
 #pragma unroll
     for (int rd = 0; rd < RR::NR; ++rd) {
         // pair p of this round packs rows 2(rd NPR + p) and 2(rd NPR + p) + 1 as a + i b
@@ -94,61 +187,29 @@ __global__ __launch_bounds__(XZShape<L>::NTA) void xz_forward_kernel(const XZBat
         for (int p = 0; p < NPR; ++p) {
             const int z0 = 2 * (rd * NPR + p);
             if (owner) {
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    const int kx = 2 * t + s;
-                    float2 Zk = buf[p * LS + lpad(kx)];
-                    float2 Zn = cconj(buf[p * LS + lpad((L2 - kx) & (L2 - 1))]);
-                    float2 d = csub(Zk, Zn);
-                    col[s][z0] = cscale(cadd(Zk, Zn), 0.5f);
-                    if (z0 + 1 < NZS) col[s][z0 + 1] = make_float2(0.5f * d.y, -0.5f * d.x);
-                }
+                float2 Zk = buf[p * LS + lpad(t)];
+                float2 Zn = cconj(buf[p * LS + lpad((L2 - t) & (L2 - 1))]);
+                float2 d = csub(Zk, Zn);
+                col[z0] = cscale(cadd(Zk, Zn), 0.5f);
+                if (z0 + 1 < NZS) col[z0 + 1] = make_float2(0.5f * d.y, -0.5f * d.x);
             }
             if (t == 0) {  // kx = L: Z[L] and conj Z[L]
                 float2 Zk = buf[p * LS + lpad(L)];
-                nyq[z0] = make_float2(Zk.x, 0.f);
-                if (z0 + 1 < NZS) nyq[z0 + 1] = make_float2(Zk.y, 0.f);
+                nyq[z0] = Zk.x;
+                if (z0 + 1 < NZS) nyq[z0 + 1] = Zk.y;
             }
         }
         __syncthreads();
     }
 
-    // z: length-NZ transform of the NZS stored rows (upper half zero):
-    // Y[2m] = DFT(x)[m], Y[2m+1] = DFT(x W_NZ^z)[m]
     const float2* twz = tw_all + tw_offset(NZ);
-    if (owner) {
-        float2 Y[2][NZ];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            if constexpr (NZS == 1) {
-                Y[s][0] = col[s][0];
-            } else {
-                float2 e[NZS], o[NZS];
-#pragma unroll
-                for (int z = 0; z < NZS; ++z) {
-                    e[z] = col[s][z];
-                    o[z] = z == 0 ? col[s][0] : cmul(col[s][z], twz[z]);
-                }
-                dft<NZS, -1>(e);
-                dft<NZS, -1>(o);
-#pragma unroll
-                for (int m = 0; m < NZS; ++m) {
-                    Y[s][2 * m] = e[m];
-                    Y[s][2 * m + 1] = o[m];
-                }
-            }
-        }
-#pragma unroll
-        for (int kz = 0; kz < NZ; ++kz) {
-            float2* d = T + t_index(c, kz, NZ, G, ny, 2 * t, y);
-            *reinterpret_cast<float4*>(d) = make_float4(Y[0][kz].x, Y[0][kz].y, Y[1][kz].x, Y[1][kz].y);
-        }
-    }
+    if (owner)
+        z_forward<NZS>(col, twz, [&](int kz, float2 v) { T[t_index(c, kz, NZ, G, ny, t, y)] = v; });
     // kx = L (real rows: its spectrum is real): direct length-NZ DFT, one output per thread
     if (t < NZ) {
         float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int z = 0; z < NZS; ++z) acc = cadd(acc, cscale(twz[(t * z) & (NZ - 1)], nyq[z].x));
+        for (int z = 0; z < NZS; ++z) acc = cadd(acc, cscale(twz[(t * z) & (NZ - 1)], nyq[z]));
         T[t_index(c, t, NZ, G, ny, L, y)] = acc;
     }
 }
@@ -238,22 +299,35 @@ __global__ __launch_bounds__(NT) void yconv_kernel(const YCBatch b, const float2
     fft_io<LNY, +1, 3, NT, Rows, false, true, true>(buf, tw, from_lds, sink);
 }
 
-// Same column work for LNY = 2 NT R (ny = 256, 512), with the radices ordered so
-// that the tensor product runs in registers: forward passes 16, 16, R and
-// inverse passes R, 16, 16.  After the forward last pass thread j holds
-// k = j + NT r (r < R) of all three component lines, which is exactly the input
-// set of butterfly j of the inverse first pass; the product sits between the
-// two in registers, with no LDS round trip.
-template <int LNY, int NZ>
-__global__ __launch_bounds__(NT) void yconv_reg_kernel(const YCBatch b, const float2* __restrict__ tw_all) {
+// Same column work for LNY = NTY R (ny >= 256 with NTY = 256 threads, ny >= 128
+// with 128), with the radices ordered so that the tensor product runs in
+// registers: forward passes 16, R1, R and inverse passes R, R1, 16
+// (R1 = LNY / (16 R)).  After the forward last pass thread j holds
+// k = j + NTY r (r < R) of all three component lines, which is exactly the
+// input set of butterfly j of the inverse first pass; the product sits between
+// the two in registers, with no LDS round trip.  The thread count fixes the
+// radix order (1024 = 16 16 4 with 256 threads, 16 8 8 with 128), so the two
+// forms round differently; each is deterministic.
+//
+// PAIR = false: a block takes one plane; the blocks of the mirror planes kz and
+// NZ - kz, which read the same folded tensor column, are adjacent in the grid.
+// PAIR = true: a block takes both mirror planes of one kx (0 and NZ/2 for the
+// first pair): the tensor values are loaded once for both, and the second
+// column's spectra are loaded into registers while the first column's passes
+// run (more registers per thread, fewer waves per SIMD).  Same arithmetic.
+template <int LNY, int NZ, int NTY, bool PAIR>
+__global__ __launch_bounds__(NTY) void yconv_reg_kernel(const YCBatch b, const float2* __restrict__ tw_all) {
+    constexpr int NT = NTY;
     constexpr int NY = LNY / 2;
-    constexpr int R = LNY / 256;
-    static_assert(R >= 2 && LNY / R == NT, "thread j owns k = j + NT r of the three lines");
+    constexpr int R = LNY / NT;
+    constexpr int R1 = LNY / (16 * R);
+    static_assert(R >= 2 && R <= 16 && R1 >= 2 && R1 <= 16 && 16 * R1 * R == LNY,
+                  "thread j owns k = j + NT r of the three lines");
     constexpr int LS = lpad_c(LNY);
     using Rows = RowLines<LS>;
     __shared__ float2 buf[3 * LS];
-    // twiddles as coarse x fine products (Tw2): 26.6 KB of LDS per block, so
-    // five blocks share a compute unit instead of four
+    // twiddles as coarse x fine products (Tw2): 26.6 KB of LDS per block at
+    // LNY = 1024, so five blocks share a compute unit instead of four
     __shared__ float2 twt[tw2_entries(LNY)];
     const Tw2 tw = stage_tw2<LNY, NT>(twt, tw_all + tw_offset(LNY));
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
@@ -261,80 +335,135 @@ __global__ __launch_bounds__(NT) void yconv_reg_kernel(const YCBatch b, const fl
     const YCDesc& d = b.d[item];
     const int X1 = d.X1, Y1 = d.Y1, Z1 = d.Z1, G = d.G;
     const int id = gid - b.start[item];
-    int kx, kz;
+    int kx, kzA, kzB;
     if constexpr (NZ == 1) {
         kx = id;
-        kz = 0;
+        kzA = kzB = 0;
+    } else if constexpr (PAIR) {
+        const int jj = id / X1;
+        kx = id - jj * X1;
+        kzA = jj;
+        kzB = jj == 0 ? NZ / 2 : NZ - jj;
     } else {
         const int member = id & 1, t = id >> 1, jj = t / X1;
         kx = t - jj * X1;
-        kz = jj == 0 ? (member ? NZ / 2 : 0) : (member ? NZ - jj : jj);
+        kzA = kzB = jj == 0 ? (member ? NZ / 2 : 0) : (member ? NZ - jj : jj);
     }
+    constexpr int NCOL = (NZ == 1 || !PAIR) ? 1 : 2;
     const size_t cstride = (size_t)NZ * G * NY * TKB;
-    float2* __restrict__ col = d.T + (((size_t)kz * G + kx / TKB) * NY) * TKB + kx % TKB;
+    auto column = [&](int kz) { return d.T + (((size_t)kz * G + kx / TKB) * NY) * TKB + kx % TKB; };
     const int j = threadIdx.x;
 
+    // first-pass inputs (radix 16, upper half of the padded line zero) of one
+    // column, held in registers: butterfly bb = j + q NT of line bb / NB
+    constexpr int NB = LNY / 16, TOT = 3 * NB, PER = (TOT + NT - 1) / NT;
+    float2 pf[PER][8];
+    auto load_column = [&](const float2* colp) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int bb = j + q * NT;
+            if (TOT % NT == 0 || bb < TOT) {
+                const int line = bb / NB, jb = bb - line * NB;
+#pragma unroll
+                for (int r = 0; r < 8; ++r) pf[q][r] = colp[line * cstride + (size_t)(jb + r * NB) * TKB];
+            }
+        }
+    };
     // tensor values of the thread's k = j + NT r, folded to f = min(k, LNY - k)
-    const int kzf = 2 * kz > NZ ? NZ - kz : kz;
-    const float sz = 2 * kz > NZ ? -1.f : 1.f;
     const size_t KC = (size_t)Z1 * X1 * Y1;
-    const float* kp = d.K + ((size_t)kzf * X1 + kx) * Y1;
     float kv[R][6], sy[R];
+    auto load_tensor = [&](int kzf) {
+        const float* kp = d.K + ((size_t)kzf * X1 + kx) * Y1;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int k = j + NT * r;
-        const int f = k <= NY ? k : LNY - k;
-        sy[r] = k <= NY ? 1.f : -1.f;
+        for (int r = 0; r < R; ++r) {
+            const int k = j + NT * r;
+            const int f = k <= NY ? k : LNY - k;
+            sy[r] = k <= NY ? 1.f : -1.f;
 #pragma unroll
-        for (int a = 0; a < 6; ++a) kv[r][a] = kp[a * KC + f];
-    }
+            for (int a = 0; a < 6; ++a) kv[r][a] = kp[a * KC + f];
+        }
+    };
 
-    auto src = [&](int c, int yy) { return col[c * cstride + (size_t)yy * TKB]; };
-    first_pass<LNY, 16, -1, 3, NT, Rows, true, false, true>(buf, src);
-    stockham_pass<LNY, 16, 16, -1, 3, NT, Rows>(buf, tw);
-    float2 v[3][R];
+    load_column(column(kzA));
+    int kzf_loaded = 2 * kzA > NZ ? NZ - kzA : kzA;
+    load_tensor(kzf_loaded);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int ci = 0; ci < NCOL; ++ci) {
+        const int kz = ci == 0 ? kzA : kzB;
+        float2* __restrict__ col = column(kz);
+        const int kzf = 2 * kz > NZ ? NZ - kz : kz;
+        const float sz = 2 * kz > NZ ? -1.f : 1.f;
+        if (kzf != kzf_loaded) {  // the first pair's second plane (NZ/2)
+            load_tensor(kzf);
+            kzf_loaded = kzf;
+        }
+        // forward first pass from the registers into LDS
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[c][r] = buf[c * LS + lpad(j + NT * r)];
+        for (int q = 0; q < PER; ++q) {
+            const int bb = j + q * NT;
+            if (TOT % NT == 0 || bb < TOT) {
+                const int line = bb / NB, jb = bb - line * NB;
+                float2 v[16];
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[c][r] = cmul(v[c][r], tw[j * r]);
-        dft<R, -1>(v[c]);
+                for (int r = 0; r < 8; ++r) v[r] = pf[q][r];
+                dft_half_in<16, -1>(v);
+                float2* dst = buf + Rows::idx(line, jb * 16);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) dst[Rows::template at<true>(jb * 16, r)] = v[r];
+            }
+        }
+        __syncthreads();
+        if (ci + 1 < NCOL) load_column(column(kzB));  // in flight during this column's passes
+        stockham_pass<LNY, R1, 16, -1, 3, NT, Rows>(buf, tw);
+        float2 v[3][R];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[c][r] = buf[c * LS + lpad(j + NT * r)];
+            dft_twiddled<R, -1>(v[c], tw, j);
+        }
+        // H^_a = sum_b K_ab M^_b at k = j + NT r
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float kxx = kv[r][0], kyy = kv[r][1], kzz = kv[r][2];
+            const float kxy = sy[r] * kv[r][3], kxz = sz * kv[r][4], kyz = sy[r] * sz * kv[r][5];
+            const float2 mx = v[0][r], my = v[1][r], mz = v[2][r];
+            auto dot3 = [](float a, float x, float bb, float yv, float cc, float zv) {
+                return fmaf(cc, zv, fmaf(bb, yv, a * x));
+            };
+            v[0][r] = make_float2(dot3(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3(kxx, mx.y, kxy, my.y, kxz, mz.y));
+            v[1][r] = make_float2(dot3(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3(kxy, mx.y, kyy, my.y, kyz, mz.y));
+            v[2][r] = make_float2(dot3(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3(kxz, mx.y, kyz, my.y, kzz, mz.y));
+        }
+        // inverse first pass (radix R, sub-size 1: no twiddles), Stockham order j R + r
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dft<R, +1>(v[c]);
+        __syncthreads();   // every thread has read its forward inputs
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[c * LS + lpad(j * R + r)] = v[c][r];
+        __syncthreads();
+        stockham_pass<LNY, R1, R, +1, 3, NT, Rows>(buf, tw);
+        auto sink = [&](int c, int yy, float2 val) { col[c * cstride + (size_t)yy * TKB] = val; };
+        last_pass<LNY, 16, +1, 3, NT, Rows, true, false>(buf, tw, sink);
+        if (ci + 1 < NCOL) __syncthreads();  // the last pass has read LDS before the next first pass writes it
     }
-    // H^_a = sum_b K_ab M^_b at k = j + NT r
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const float kxx = kv[r][0], kyy = kv[r][1], kzz = kv[r][2];
-        const float kxy = sy[r] * kv[r][3], kxz = sz * kv[r][4], kyz = sy[r] * sz * kv[r][5];
-        const float2 mx = v[0][r], my = v[1][r], mz = v[2][r];
-        auto dot3 = [](float a, float x, float bb, float yv, float cc, float zv) {
-            return fmaf(cc, zv, fmaf(bb, yv, a * x));
-        };
-        v[0][r] = make_float2(dot3(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3(kxx, mx.y, kxy, my.y, kxz, mz.y));
-        v[1][r] = make_float2(dot3(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3(kxy, mx.y, kyy, my.y, kyz, mz.y));
-        v[2][r] = make_float2(dot3(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3(kxz, mx.y, kyz, my.y, kzz, mz.y));
-    }
-    // inverse first pass (radix R, sub-size 1: no twiddles), Stockham order j R + r
-#pragma unroll
-    for (int c = 0; c < 3; ++c) dft<R, +1>(v[c]);
-    __syncthreads();   // every thread has read its forward inputs
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int r = 0; r < R; ++r) buf[c * LS + lpad(j * R + r)] = v[c][r];
-    __syncthreads();
-    stockham_pass<LNY, 16, R, +1, 3, NT, Rows>(buf, tw);
-    auto sink = [&](int c, int yy, float2 val) { col[c * cstride + (size_t)yy * TKB] = val; };
-    last_pass<LNY, 16, +1, 3, NT, Rows, true, false>(buf, tw, sink);
 }
 
 // ============================================================================ xz inverse
-template <int L, int NZS>
+// One block: component c, row y.  Thread t reads column kx = t of every kz
+// plane, runs the truncated z inverse in registers (nz outputs), then NPR row
+// pairs per round are rebuilt in LDS as Hermitian-packed length-2L lines
+// (Z[k] = X_a[k] + i X_b[k], Z[2L-k] = conj X_a[k] + i conj X_b[k]) and
+// inverse transformed, keeping the first L outputs (real part row z, imaginary
+// part row z+1).
+template <int L, int NZS, int V>
 __global__ __launch_bounds__(XZShape<L>::NTA) void xz_inverse_kernel(const XZBatch b,
                                                                    const float2* __restrict__ tw_all) {
     using S = XZShape<L>;
     using Z = ZShape<NZS>;
-    using RR = XZRounds<L, NZS>;
+    using RR = XZRounds<L, NZS, V>;
     constexpr int NTA = S::NTA, L2 = S::L2, LS = S::LS, NZ = Z::NZ, NPR = RR::NPR;
     __shared__ float2 buf[NPR * LS];
     __shared__ float2 tw2[L2];
@@ -349,39 +478,18 @@ __global__ __launch_bounds__(XZShape<L>::NTA) void xz_inverse_kernel(const XZBat
     const int G = (L + 1 + TKB - 1) / TKB;
     const float2* __restrict__ T = b.d[item].T;
     float* __restrict__ rows = b.d[item].H + ((size_t)c * NZS * ny + y) * L;
-    const bool owner = t < L / 2;
+    const bool owner = t < L;
     const float2* twz = tw_all + tw_offset(NZ);
 
-    // z: truncated inverse, h[z] = IE[z] + W_NZ^-z IO[z] (IE, IO: inverses of the
-    // even and odd kz inputs), for the two owned columns
-    float2 col[2][NZS];
-    if (owner) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int kx = 2 * t + s;
-            if constexpr (NZS == 1) {
-                col[s][0] = T[t_index(c, 0, NZ, G, ny, kx, y)];
-            } else {
-                float2 e[NZS], o[NZS];
-#pragma unroll
-                for (int m = 0; m < NZS; ++m) {
-                    e[m] = T[t_index(c, 2 * m, NZ, G, ny, kx, y)];
-                    o[m] = T[t_index(c, 2 * m + 1, NZ, G, ny, kx, y)];
-                }
-                dft<NZS, +1>(e);
-                dft<NZS, +1>(o);
-#pragma unroll
-                for (int z = 0; z < NZS; ++z)
-                    col[s][z] = z == 0 ? cadd(e[0], o[0]) : cadd(e[z], cmul(cconj(twz[z]), o[z]));
-            }
-        }
-    }
+    float2 col[NZS];
+    if (owner)
+        z_inverse<NZS>(col, twz, [&](int kz) { return T[t_index(c, kz, NZ, G, ny, t, y)]; });
     // kx = L: direct truncated inverse (only the real part is used: the row is real)
     if (t < NZS) {
         float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
         for (int k = 0; k < NZ; ++k)
-            acc = cadd(acc, cmul(cconj(twz[(k * t) & (NZ - 1)]), T[t_index(c, k, NZ, G, ny, L, y)]));
+            acc = cmad(cconj(twz[(k * t) & (NZ - 1)]), T[t_index(c, k, NZ, G, ny, L, y)], acc);
         nyq[t] = acc.x;
     }
     __syncthreads();
@@ -394,18 +502,14 @@ __global__ __launch_bounds__(XZShape<L>::NTA) void xz_inverse_kernel(const XZBat
         for (int p = 0; p < NPR; ++p) {
             const int z0 = 2 * (rd * NPR + p);
             if (owner) {
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    const int kx = 2 * t + s;
-                    float2 Xa = col[s][z0];
-                    float2 Xb = (z0 + 1 < NZS) ? col[s][z0 + 1] : make_float2(0.f, 0.f);
-                    if (kx == 0) {
-                        Xa.y = 0.f;
-                        Xb.y = 0.f;
-                    }
-                    buf[p * LS + lpad(kx)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
-                    if (kx > 0) buf[p * LS + lpad(L2 - kx)] = make_float2(Xa.x + Xb.y, Xb.x - Xa.y);
+                float2 Xa = col[z0];
+                float2 Xb = (z0 + 1 < NZS) ? col[z0 + 1] : make_float2(0.f, 0.f);
+                if (t == 0) {
+                    Xa.y = 0.f;
+                    Xb.y = 0.f;
                 }
+                buf[p * LS + lpad(t)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
+                if (t > 0) buf[p * LS + lpad(L2 - t)] = make_float2(Xa.x + Xb.y, Xb.x - Xa.y);
             }
             if (t == 0) buf[p * LS + lpad(L)] = make_float2(nyq[z0], (z0 + 1 < NZS) ? nyq[z0 + 1] : 0.f);
         }
@@ -424,7 +528,7 @@ __global__ __launch_bounds__(XZShape<L>::NTA) void xz_inverse_kernel(const XZBat
 // ============================================================================ launchers
 bool xz_supported(int nx, int ny, int nz) {
     auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
-    return pow2(nx) && pow2(ny) && pow2(nz) && nx >= 32 && nx <= 1024 && ny >= 16 && ny <= 512 &&
+    return pow2(nx) && pow2(ny) && pow2(nz) && nx >= 32 && nx <= 1024 && ny >= 16 && ny <= 1024 &&
            nz <= 16;
 }
 
@@ -440,22 +544,28 @@ size_t xz_t_elems(int nx, int ny, int nz) {
 #define DM_XZ_L_CASES(MACRO) MACRO(32) MACRO(64) MACRO(128) MACRO(256) MACRO(512) MACRO(1024)
 
 template <bool INVERSE>
-static int launch_xz(XZBatch b, int nx, int nz, const float2* tw, hipStream_t s) {
+static int launch_xz(XZBatch b, int nx, int nz, int variant, const float2* tw, hipStream_t s) {
     if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "xz stage: bad batch size");
     b.start[0] = 0;
     for (int r = 0; r < b.count; ++r) b.start[r + 1] = b.start[r] + 3 * b.d[r].ny;
     const unsigned grid = (unsigned)b.start[b.count];
     bool done = false;
-#define NZS_CASE(NZv)                                                                         \
-    if (nz == NZv) {                                                                          \
-        constexpr int NZS = NZv;                                                              \
-        if (INVERSE)                                                                          \
-            hipLaunchKernelGGL((xz_inverse_kernel<L, NZS>), dim3(grid), dim3(XZShape<L>::NTA), \
-                               0, s, b, tw);                                                  \
-        else                                                                                  \
-            hipLaunchKernelGGL((xz_forward_kernel<L, NZS>), dim3(grid), dim3(XZShape<L>::NTA), \
-                               0, s, b, tw);                                                  \
-        done = true;                                                                          \
+#define XZ_LAUNCH(V)                                                                               \
+    if (INVERSE)                                                                                   \
+        hipLaunchKernelGGL((xz_inverse_kernel<L, NZS, V>), dim3(grid), dim3(XZShape<L>::NTA), 0, s, \
+                           b, tw);                                                                 \
+    else                                                                                           \
+        hipLaunchKernelGGL((xz_forward_kernel<L, NZS, V>), dim3(grid), dim3(XZShape<L>::NTA), 0, s, \
+                           b, tw);
+#define NZS_CASE(NZv)                       \
+    if (nz == NZv) {                        \
+        constexpr int NZS = NZv;            \
+        switch (variant) {                  \
+            case 0: XZ_LAUNCH(0) break;     \
+            case 1: XZ_LAUNCH(1) break;     \
+            default: XZ_LAUNCH(2) break;    \
+        }                                   \
+        done = true;                        \
     }
 #define L_CASE(Lv)                  \
     if (nx == Lv) {                 \
@@ -465,38 +575,56 @@ static int launch_xz(XZBatch b, int nx, int nz, const float2* tw, hipStream_t s)
     DM_XZ_L_CASES(L_CASE)
 #undef L_CASE
 #undef NZS_CASE
+#undef XZ_LAUNCH
     if (!done) return fail(DEMAG_EUNSUPPORTED, "xz stage: unsupported mesh");
     DM_CHECK_LAUNCH();
     return DEMAG_OK;
 }
 
-int launch_xz_forward(XZBatch b, int nx, int nz, const float2* tw, hipStream_t s) {
-    return launch_xz<false>(b, nx, nz, tw, s);
+int launch_xz_forward(XZBatch b, int nx, int nz, int variant, const float2* tw, hipStream_t s) {
+    return launch_xz<false>(b, nx, nz, variant, tw, s);
 }
-int launch_xz_inverse(XZBatch b, int nx, int nz, const float2* tw, hipStream_t s) {
-    return launch_xz<true>(b, nx, nz, tw, s);
+int launch_xz_inverse(XZBatch b, int nx, int nz, int variant, const float2* tw, hipStream_t s) {
+    return launch_xz<true>(b, nx, nz, variant, tw, s);
 }
 
-int launch_yconv(YCBatch b, int ny, int Nz, const float2* tw, hipStream_t s) {
+// Register-product kernel (LNY = 2 ny >= 512): variant 0 = 128 threads, one
+// plane per block (radix order 16, R1, R with R = LNY / 128; LNY <= 1024, else
+// as variant 1); 1 = 256 threads, one plane per block; 2 = 256 threads, both
+// mirror planes per block.  Variants 1 and 2 give the same bits.
+static bool yconv_pairs(int ny, int Nz, int variant) {
+    return 2 * ny >= 512 && Nz > 1 && variant == 2;
+}
+int launch_yconv(YCBatch b, int ny, int Nz, int variant, const float2* tw, hipStream_t s) {
     if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "y conv: bad batch size");
+    const int planes_per_block = yconv_pairs(ny, Nz, variant) ? 2 : 1;
     b.start[0] = 0;
-    for (int r = 0; r < b.count; ++r) b.start[r + 1] = b.start[r] + Nz * b.d[r].X1;
+    for (int r = 0; r < b.count; ++r) b.start[r + 1] = b.start[r] + Nz / planes_per_block * b.d[r].X1;
     const unsigned grid = (unsigned)b.start[b.count];
     bool done = false;
-#define NZ_CASE(NZv)                                                                                 \
-    if (Nz == NZv) {                                                                                 \
-        if constexpr (LNY >= 2 * NT)                                                                 \
-            hipLaunchKernelGGL((yconv_reg_kernel<LNY, NZv>), dim3(grid), dim3(NT), 0, s, b, tw);     \
-        else                                                                                         \
-            hipLaunchKernelGGL((yconv_kernel<LNY, NZv>), dim3(grid), dim3(NT), 0, s, b, tw);         \
-        done = true;                                                                                 \
+#define NZ_CASE(NZv)                                                                                  \
+    if (Nz == NZv) {                                                                                  \
+        if constexpr (LNY >= 2 * NT) {                                                                \
+            if (LNY <= 1024 && variant == 0)                                                          \
+                hipLaunchKernelGGL((yconv_reg_kernel<LNY, NZv, (LNY <= 1024 ? 128 : 256), false>),    \
+                                   dim3(grid), dim3(LNY <= 1024 ? 128 : 256), 0, s, b, tw);           \
+            else if (variant == 2)                                                                    \
+                hipLaunchKernelGGL((yconv_reg_kernel<LNY, NZv, 256, true>), dim3(grid), dim3(256), 0, \
+                                   s, b, tw);                                                         \
+            else                                                                                      \
+                hipLaunchKernelGGL((yconv_reg_kernel<LNY, NZv, 256, false>), dim3(grid), dim3(256), 0, \
+                                   s, b, tw);                                                         \
+        } else {                                                                                      \
+            hipLaunchKernelGGL((yconv_kernel<LNY, NZv>), dim3(grid), dim3(NT), 0, s, b, tw);          \
+        }                                                                                             \
+        done = true;                                                                                  \
     }
 #define Y_CASE(NYv)                     \
     if (ny == NYv) {                    \
         constexpr int LNY = 2 * NYv;    \
         NZ_CASE(1) NZ_CASE(4) NZ_CASE(8) NZ_CASE(16) NZ_CASE(32) \
     }
-    Y_CASE(16) Y_CASE(32) Y_CASE(64) Y_CASE(128) Y_CASE(256) Y_CASE(512)
+    Y_CASE(16) Y_CASE(32) Y_CASE(64) Y_CASE(128) Y_CASE(256) Y_CASE(512) Y_CASE(1024)
 #undef Y_CASE
 #undef NZ_CASE
     if (!done) return fail(DEMAG_EUNSUPPORTED, "y conv: unsupported mesh");

@@ -47,9 +47,11 @@ SHAPES = [
     (32, 32, 4), (1, 1, 1), (2, 1, 1), (1, 8, 1), (8, 1, 1), (16, 1, 4), (4, 4, 2),
     (8, 8, 8), (64, 32, 8), (128, 64, 2), (32, 64, 1), (8, 4, 64), (4, 4, 128),
     (256, 16, 2), (16, 256, 1), (2048, 4, 1), (4, 2048, 2),
-    # three-kernel thin-mesh form (32 <= nx <= 1024, 16 <= ny <= 512, nz <= 16)
+    # three-kernel thin-mesh form (32 <= nx <= 1024, 16 <= ny <= 1024, nz <= 16)
     (1024, 64, 4), (512, 32, 16), (128, 512, 16), (64, 16, 16), (32, 16, 1), (1024, 16, 16),
-    (256, 128, 8), (32, 512, 2),
+    (256, 128, 8), (32, 512, 2), (64, 1024, 2), (256, 1024, 1), (32, 1024, 16),
+    # five-pass form beside it (n_z = 32)
+    (32, 16, 32), (128, 32, 32),
 ]
 
 
@@ -222,6 +224,52 @@ def test_variants_are_bit_identical(gpu_lib, torch_dev, n):
         assert torch.equal(H, ref)
         Href = odemag.demag_fft(M.cpu().numpy().astype(np.float64), W.CELL_4NM)
         assert max(odemag.rel_l2_per_field(ref.cpu().numpy(), Href)) <= TOL
+    finally:
+        pkg.demag_destroy(plan)
+
+
+@pytest.mark.parametrize("n", [(64, 256, 4), (32, 512, 2), (1024, 32, 16), (32, 1024, 2)],
+                         ids=lambda n: "x".join(map(str, n)))
+def test_thin_form_variants(gpu_lib, torch_dev, n):
+    """Thin-mesh form: the row pairs per round of the two xz kernels (variants of
+    stages 0 and 4) give the same bits; the y convolution's variants (0: 128
+    threads, radix order 16 8 8; 1: 256 threads, 16 16 4, one plane per block;
+    2: as 1 with both mirror planes per block) each meet the contract against
+    the oracle, 1 and 2 bit for bit the same; the autotuned plan reproduces the
+    bits of the variants it picked."""
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    _say("thin-form variants", n)
+    plan = pkg.demag_setup(n + W.CELL_4NM)
+    try:
+        assert pkg.demag_get_form(plan) == pkg.DEMAG_FORM_THIN
+        M = torch.from_numpy(W.magnetisation(n, 9)).cuda()
+        Href = odemag.demag_fft(M.cpu().numpy().astype(np.float64), W.CELL_4NM)
+        per_conv = {}
+        for vc in (0, 1, 2):
+            pkg.demag_set_variant(plan, 2, vc)
+            ref = None
+            for v in range(pkg.NVARIANTS):
+                pkg.demag_set_variant(plan, 0, v)
+                pkg.demag_set_variant(plan, 4, (v + 1) % pkg.NVARIANTS)
+                H = torch.empty_like(M)
+                pkg.demag_field(plan, M, H)
+                torch.cuda.synchronize()
+                if ref is None:
+                    ref = H
+                assert torch.equal(H, ref), (vc, v)
+            errs = odemag.rel_l2_per_field(ref.cpu().numpy().astype(np.float64), Href)
+            _say("  y conv variant", vc, "rel-L2", errs)
+            assert max(errs) <= TOL, (vc, errs)
+            per_conv[vc] = ref
+        assert torch.equal(per_conv[1], per_conv[2])
+        pkg.demag_autotune(plan)
+        chosen = [pkg.demag_get_variant(plan, st) for st in range(5)]
+        _say("  autotuned variants", chosen)
+        H = torch.empty_like(M)
+        pkg.demag_field(plan, M, H)
+        torch.cuda.synchronize()
+        assert torch.equal(H, per_conv[chosen[2]])
     finally:
         pkg.demag_destroy(plan)
 
