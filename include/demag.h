@@ -195,6 +195,27 @@ int llg_step(demag_plan* plan, float* m, const llg_params* params, double dt,
              int32_t nsteps, void* stream);
 
 /*
+ * llg_step_noalloc -- the steps of llg_step for callers that cannot allocate
+ * device memory: code under HIP stream capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  Same arithmetic and launches as llg_step
+ * stepping one by one, so m comes out bitwise the same; the steps are launched
+ * eagerly (no graph), and the plan must already exist (demag_setup allocates).
+ * The RK4 stage buffers (12 N floats) are a fixed 64 MiB device array in the
+ * library, one copy per GPU held until the process ends, so
+ *   N <= llg_noalloc_max_cells() = 1,398,101 cells.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (other streams or threads) race and must be serialised by the caller.
+ *   m       in/out device FP32 [3][nz][ny][nx], unit vectors, updated in place.
+ * Errors: EINVAL (null, nsteps < 0, dt not finite, bad params, mesh above the
+ * limit, current device not the plan's), EUNSUPPORTED (DEMAG_EXTRAPOLATE_HD
+ * plans, which keep an H_d history), EHIP.
+ */
+int llg_step_noalloc(demag_plan* plan, float* m, const llg_params* params, double dt,
+                     int32_t nsteps, void* stream);
+/* The largest mesh (cells) llg_step_noalloc accepts. */
+size_t llg_noalloc_max_cells(void);
+
+/*
  * llg_reset -- discard the H_d history of a DEMAG_EXTRAPOLATE_HD plan, so that
  * the next llg_step starts a new trajectory (call it after setting m to a state
  * that does not continue the previous steps).  No effect on other plans.

@@ -50,7 +50,7 @@ EXPORTS = (
     "demag_timing_enable",
     "demag_timing_read", "demag_autotune", "demag_set_variant", "demag_get_variant",
     "demag_set_chunks", "demag_get_chunks", "demag_get_form", "serve_open", "serve_submit", "serve_wait",
-    "serve_get_stats", "serve_close", "demag_last_error",
+    "serve_get_stats", "serve_close", "demag_last_error", "llg_step_noalloc", "llg_noalloc_max_cells",
 )
 SERVE_GRAPHS = 1
 NVARIANTS = 3
@@ -120,6 +120,8 @@ def load(path=None):
         "demag_destroy": ([vp], ctypes.c_int),
         "llg_step": ([vp, vp, P(llg_params), ctypes.c_double, ctypes.c_int32, vp], ctypes.c_int),
         "llg_reset": ([vp], ctypes.c_int),
+        "llg_step_noalloc": ([vp, vp, P(llg_params), ctypes.c_double, ctypes.c_int32, vp], ctypes.c_int),
+        "llg_noalloc_max_cells": ([], sz),
         "demag_field_mean": ([vp, vp, vp, vp], ctypes.c_int),
         "atom_setup": ([P(atom_mesh), ctypes.c_uint32, vp, P(vp)], ctypes.c_int),
         "atom_step": ([vp, vp, P(atom_params), ctypes.c_double, ctypes.c_int32, vp], ctypes.c_int),
@@ -210,6 +212,20 @@ def llg_step(plan, m, params, dt, nsteps, stream=None):
         Ms, A, alpha, gamma, hz = params
         params = llg_params(Ms, A, alpha, gamma, (ctypes.c_double * 3)(*hz))
     return _check(load().llg_step(plan, _ptr(m), ctypes.byref(params), dt, nsteps, _stream(stream)))
+
+
+def llg_step_noalloc(plan, m, params, dt, nsteps, stream=None):
+    """llg_step without device allocation (RK4 buffers in the library's fixed
+    per-GPU array; meshes up to llg_noalloc_max_cells() cells)."""
+    if not isinstance(params, llg_params):
+        Ms, A, alpha, gamma, hz = params
+        params = llg_params(Ms, A, alpha, gamma, (ctypes.c_double * 3)(*hz))
+    return _check(load().llg_step_noalloc(plan, _ptr(m), ctypes.byref(params), dt, nsteps,
+                                          _stream(stream)))
+
+
+def llg_noalloc_max_cells():
+    return int(load().llg_noalloc_max_cells())
 
 
 def demag_field_mean(plan, v, out, stream=None):

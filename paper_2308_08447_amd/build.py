@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdemag.so")
 SOURCES = ["capi.hip", "stages_x.hip", "stages_y.hip", "stages_z.hip", "stages_xz.hip", "tensor.hip",
            "dynamics.hip",
-           "serve.hip"]
+           "serve.hip", "noalloc.hip"]
 ARCH = os.environ.get("DEMAG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
