@@ -120,7 +120,16 @@ def cpu_baseline(n, cell, budget_s=20.0, one_thread=True):
         times.append(time.perf_counter() - t0)
     t = float(np.median(times))
     cells = n[0] * n[1] * n[2]
+    # the same steps in FP32 (SciPy single-precision transforms), for a
+    # like-for-like figure beside the FP32 GPU path
+    op32 = op.to_float32()
     del op
+    M32 = M.astype(np.float32)
+    op32(M32)
+    t0 = time.perf_counter()
+    op32(M32)
+    t32 = time.perf_counter() - t0
+    del op32
     t1 = None
     if one_thread:  # one evaluation on a single thread, for a per-core figure
         op1 = odemag.DemagFFT(n, cell, workers=1)
@@ -138,6 +147,7 @@ def cpu_baseline(n, cell, budget_s=20.0, one_thread=True):
                       f"(scipy rfftn/irfftn, workers={workers}; tensor set-up excluded), "
                       f"median {t:.3f} s each",
             "setup_s": round(t_setup, 2),
+            "fp32_scipy_gcells_per_s": round(cells / t32 / 1e9, 6),
             "one_thread_gcells_per_s": round(cells / t1 / 1e9, 6) if t1 else None, "cpu_model": model}
 
 
@@ -247,7 +257,13 @@ def _field_run(pkg, n, cell, flags, M, H, args, stream, label):
     print(f"{label}: set-up", file=sys.stderr, flush=True)
     plan = pkg.demag_setup(n + cell, flags, stream=stream)
     try:
-        pkg.demag_autotune(plan, stream)
+        if args.variants or args.chunks:  # pinned schedule (profiler runs), else autotuned
+            for st, v in enumerate(args.variants or []):
+                pkg.demag_set_variant(plan, st, v)
+            if args.chunks:
+                pkg.demag_set_chunks(plan, args.chunks)
+        else:
+            pkg.demag_autotune(plan, stream)
         nch = pkg.demag_get_chunks(plan)
         form = pkg.demag_get_form(plan)
         _LAST_VARIANTS[:] = [pkg.demag_get_variant(plan, st) for st in range(5)]

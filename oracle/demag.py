@@ -88,11 +88,15 @@ class DemagFFT:
     initialisation stage, Sec. II).
     """
 
-    def __init__(self, n, cell, workers=None, kind="newell"):
+    def __init__(self, n, cell, workers=None, kind="newell", dtype=np.float64):
+        """dtype: np.float64 (the oracle) or np.float32, the same steps in single
+        precision (the transformed tensor rounded once from FP64), used only to
+        time a like-for-like CPU figure, never as a reference."""
         self.n = tuple(int(v) for v in n)  # (nx, ny, nz)
         self.cell = tuple(float(c) for c in cell)
         self.N = padded_size(self.n)  # (Nx, Ny, Nz)
         self.workers = workers
+        self.dtype = np.dtype(dtype)
         nx, ny, nz = self.n
         Nx, Ny, Nz = self.N
         kk, jj, ii = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
@@ -108,11 +112,21 @@ class DemagFFT:
                     * np.where(sy, py, 1)[None, :, None]
                     * np.where(sx, px, 1)[None, None, :])
             Kpad = octant[c][np.ix_(az, ay, ax)] * sign * used
-            self.Khat.append(sfft.rfftn(Kpad, axes=(0, 1, 2), workers=workers))
-            del Kpad
+            Kh = sfft.rfftn(Kpad, axes=(0, 1, 2), workers=workers)
+            self.Khat.append(Kh.astype(np.complex64) if self.dtype == np.float32 else Kh)
+            del Kpad, Kh
+
+    def to_float32(self):
+        """The same operator computing in FP32 (tensor rounded once from FP64);
+        for timing only."""
+        op = object.__new__(DemagFFT)
+        op.__dict__.update(self.__dict__)
+        op.dtype = np.dtype(np.float32)
+        op.Khat = [k.astype(np.complex64) for k in self.Khat]
+        return op
 
     def __call__(self, M):
-        M = np.asarray(M, dtype=np.float64)
+        M = np.asarray(M, dtype=self.dtype)
         nx, ny, nz = self.n
         Nx, Ny, Nz = self.N
         assert M.shape == (3, nz, ny, nx), M.shape
