@@ -28,6 +28,7 @@
 #include <deque>
 #include <map>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -81,6 +82,7 @@ struct demag_server {
     std::vector<Request*> ready;         // set up, not yet in the active set
     std::vector<Request*> active;
     int admitted = 0;                    // preparing + ready + active
+    int in_prep = 0;                     // requests the preparation thread is setting up
     std::unordered_map<uint64_t, Request*> reqs;
     std::map<ShapeKey, int> active_shapes;  // active requests per mesh (tensor held once)
     uint64_t next_id = 1;
@@ -168,40 +170,58 @@ void admit(demag_server* s) {
 }
 
 // Preparation thread: plan (tensor set-up on first use of a mesh), RK4
-// buffers, m0 upload, on its own stream; the request is then ready to join the
-// active set.
+// buffers, m0 upload, on its own stream.  It takes every request admitted so
+// far as one group and hands the group over when all of it is ready, so a
+// burst of arrivals joins the active set together.
 void prep_main(demag_server* s) {
     (void)hipSetDevice(s->device);
     for (;;) {
-        Request* r = nullptr;
+        std::deque<Request*> group;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_prep.wait(lk, [&] { return s->stop || !s->preparing.empty(); });
             if (s->stop) return;
-            r = s->preparing.front();
-            s->preparing.pop_front();
+            group.swap(s->preparing);
+            s->in_prep = (int)group.size();
         }
-        int rc = dm::create_plan(&r->mesh, DEMAG_FP32, s->prep_stream, &r->plan);
-        if (!rc) rc = dm::ensure_rk(r->plan);
-        if (!rc) rc = dm::dev_alloc((void**)&r->m, r->host.size() * sizeof(float), "request m");
-        if (!rc && hipMemcpyAsync(r->m, r->host.data(), r->host.size() * sizeof(float),
-                                  hipMemcpyHostToDevice, s->prep_stream) != hipSuccess)
-            rc = dm::fail(DEMAG_EHIP, "copy of m0 to the device failed");
-        if (!rc && hipStreamSynchronize(s->prep_stream) != hipSuccess)
-            rc = dm::fail(DEMAG_EHIP, "stream synchronisation failed");
-        std::string err = rc ? std::string(demag_last_error()) : std::string();
-        if (rc) release(s, r);
+        std::vector<std::tuple<Request*, int, std::string>> failed;
+        std::vector<Request*> ok;
+        for (Request* r : group) {
+            int rc = dm::create_plan(&r->mesh, DEMAG_FP32, s->prep_stream, &r->plan);
+            if (!rc) rc = dm::ensure_rk(r->plan);
+            if (!rc) rc = dm::dev_alloc((void**)&r->m, r->host.size() * sizeof(float), "request m");
+            if (!rc && hipMemcpyAsync(r->m, r->host.data(), r->host.size() * sizeof(float),
+                                      hipMemcpyHostToDevice, s->prep_stream) != hipSuccess)
+                rc = dm::fail(DEMAG_EHIP, "copy of m0 to the device failed");
+            if (rc) {
+                failed.emplace_back(r, rc, std::string(demag_last_error()));
+                release(s, r);
+            } else {
+                ok.push_back(r);
+            }
+        }
+        if (!ok.empty() && hipStreamSynchronize(s->prep_stream) != hipSuccess) {
+            for (Request* r : ok) {
+                failed.emplace_back(r, DEMAG_EHIP, "stream synchronisation failed");
+                release(s, r);
+            }
+            ok.clear();
+        }
         std::lock_guard<std::mutex> lk(s->mu);
-        if (rc) {
+        for (auto& f : failed) {
+            Request* r = std::get<0>(f);
             s->used -= admission_bytes_release(s, r);
             s->admitted--;
-            finish(s, r, rc, err);
-            s->cv_done.notify_all();
-        } else {
+            finish(s, r, std::get<1>(f), std::get<2>(f));
+        }
+        const auto now = Clock::now();
+        for (Request* r : ok) {
             r->state = Request::READY;
-            r->t_ready = Clock::now();
+            r->t_ready = now;
             s->ready.push_back(r);
         }
+        s->in_prep = 0;
+        if (!failed.empty()) s->cv_done.notify_all();
         s->cv_work.notify_one();
     }
 }
@@ -304,7 +324,8 @@ void worker_main(demag_server* s) {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait(lk, [&] {
                 return s->stop || !s->active.empty() || !s->ready.empty() ||
-                       (!s->queue.empty() && s->admitted < s->max_active && s->preparing.empty());
+                       (!s->queue.empty() && s->admitted < s->max_active && s->preparing.empty() &&
+                        s->in_prep == 0);
             });
             if (s->stop) return;
         }
@@ -317,7 +338,7 @@ void worker_main(demag_server* s) {
             // MERGE_COUNT are waiting or the oldest has waited MERGE_WAIT.
             std::lock_guard<std::mutex> lk(s->mu);
             const bool merge = !s->ready.empty() &&
-                               (s->active.empty() || s->preparing.empty() ||
+                               (s->active.empty() || (s->preparing.empty() && s->in_prep == 0) ||
                                 (int)s->ready.size() >= MERGE_COUNT ||
                                 Clock::now() - s->ready.front()->t_ready >= MERGE_WAIT);
             if (merge) {

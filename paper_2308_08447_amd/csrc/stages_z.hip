@@ -125,6 +125,172 @@ __global__ __launch_bounds__(NT) void z_convolve_kernel(const ZBatch b,
 }
 
 
+// Lean form of the same stage for power-of-two N_y and open z in FP32: every
+// index is a shift or a mask, global memory is touched only in two coalesced
+// loops (consecutive threads on consecutive ky), and the transforms run in LDS
+// on line-major rows (RowLines).  A tile pairs the folded ky = f0 .. f0+TH-1
+// with the mirrors ky = N_y - f of f = f0+1 .. f0+TH, i.e. the aligned run
+// N_y - f0 - TH .. N_y - f0 - 1 (the mirror of f = N_y/2 is the Nyquist column
+// itself), so both runs start on a TH-element boundary and every cache line a
+// tile touches is used whole; the tensor tile holds f = f0 .. f0+TH.  A block
+// takes CPB consecutive tiles of one kx: the next tile's spectra and tensor
+// values are loaded into registers while the current tile is transformed.  Per
+// column the arithmetic is that of the kernel above, so both give the same
+// bits.  Requires N_y / 2 to be a multiple of CPB TH.
+template <int NZ, int TH, int CPB>
+__global__ __launch_bounds__(NT) void z_convolve_lean_kernel(const ZBatch b,
+                                                             const float2* __restrict__ tw_all) {
+    static_assert(NZ >= 2 && (NZ & (NZ - 1)) == 0 && (TH & (TH - 1)) == 0, "powers of two");
+    constexpr int NZH = NZ / 2;                  // stored z planes
+    constexpr int KT = NZ / 2 + 1;               // folded kz values
+    constexpr int NC = 2 * TH;                   // columns per tile (ky and mirrors)
+    constexpr int NLN = 3 * NC;                  // lines (component, column)
+    constexpr int LS = lpad_c(NZ) + 1;           // line stride in LDS
+    constexpr int LNC = ilog2c(NC), LNZH = ilog2c(NZH);
+    static_assert(NT % NC == 0, "a thread keeps its column across the I/O loops");
+    constexpr int NE = 3 * NZH * NC;             // elements of a tile in one direction
+    constexpr int PE = (NE + NT - 1) / NT;
+    constexpr int NKL = 6 * KT * TH;             // tensor values f0 .. f0+TH-1 of a tile
+    constexpr int PK = (NKL + NT - 1) / NT;
+    constexpr int NKN = 6 * KT;                  // and those of f0 + TH
+    constexpr int PN = (NKN + NT - 1) / NT;
+    using Rows = RowLines<LS>;
+    __shared__ float2 buf[NLN * LS];
+    __shared__ float ks[6 * KT * (TH + 1)];      // [comp][kz][f - f0]
+    __shared__ float2 twZ[NZ];
+    stage_table(twZ, tw_all + tw_offset(NZ), NZ);
+    const int tid = threadIdx.x;
+    const int gid = xcd_tile(blockIdx.x, gridDim.x);
+    const int item = batch_item(b, gid);
+    float2* __restrict__ S2 = b.d[item].S2;
+    const float* __restrict__ K = b.d[item].K;
+    const int X1 = b.d[item].X1, Ny = b.d[item].Ny, Y1 = b.d[item].Y1, Z1 = b.d[item].Z1;
+    const int k0 = b.d[item].k0, xc = b.d[item].xc;
+    const int nbt = (Ny >> 1) / (TH * CPB);      // blocks per kx
+    const int id = gid - b.start[item];
+    const int kl = id / nbt, kx = k0 + kl;
+    const int fb = (id - kl * nbt) * (TH * CPB);  // first folded ky of the block
+    const uint32_t P = (uint32_t)xc * (uint32_t)Ny;   // complex elements per z plane of the chunk
+    const uint32_t cstride = (uint32_t)NZH * P;
+    float2* __restrict__ col = S2 + (size_t)kl * Ny;
+    const float* __restrict__ kcol = K + (size_t)kx * Y1;
+    const size_t kplane = (size_t)X1 * Y1;        // tensor values per (comp, kz) plane
+    // the column this thread loads and stores: j < TH ky = f0 + j; j = TH + u the
+    // mirror run, ky = Ny - f0 - TH + u (folded f = f0 + TH - u)
+    const int jt = tid & (NC - 1);
+    auto ky_of = [&](int f0) { return jt < TH ? f0 + jt : Ny - f0 - NC + jt; };
+    float2 v[PE];
+    float kr[PK];
+    auto load_tile = [&](int f0) {
+        const int ky = ky_of(f0);
+#pragma unroll
+        for (int i = 0; i < PE; ++i) {
+            const int e = tid + i * NT;
+            if (NE % NT == 0 || e < NE) {
+                const int z = (e >> LNC) & (NZH - 1), c = e >> (LNC + LNZH);
+                v[i] = col[c * cstride + (uint32_t)z * P + ky];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PK; ++q) {
+            const int it = tid + q * NT;
+            if (NKL % NT == 0 || it < NKL) {
+                const int jj = it & (TH - 1), rest = it / TH;   // rest = comp KT + kz
+                const int kz = rest % KT, comp = rest / KT;
+                kr[q] = kcol[((size_t)comp * Z1 + kz) * kplane + f0 + jj];
+            }
+        }
+    };
+    float kn[PN];  // the tile's last tensor values, f = f0 + TH
+    auto load_last = [&](int f0) {
+#pragma unroll
+        for (int q = 0; q < PN; ++q) {
+            const int it = tid + q * NT;
+            if (NKN % NT == 0 || it < NKN) {
+                const int kz = it % KT, comp = it / KT;
+                kn[q] = kcol[((size_t)comp * Z1 + kz) * kplane + f0 + TH];
+            }
+        }
+    };
+    load_tile(fb);
+    load_last(fb);
+    auto lds_src = [&](int line, int i) { return buf[line * LS + lpad(i)]; };
+    auto lds_sink = [&](int line, int k, float2 w) { buf[line * LS + lpad(k)] = w; };
+#pragma unroll
+    for (int t = 0; t < CPB; ++t) {
+        const int f0 = fb + t * TH;
+        const int ky = ky_of(f0);
+#pragma unroll
+        for (int i = 0; i < PE; ++i) {
+            const int e = tid + i * NT;
+            if (NE % NT == 0 || e < NE) {
+                const int z = (e >> LNC) & (NZH - 1), c = e >> (LNC + LNZH);
+                buf[(c * NC + jt) * LS + lpad(z)] = v[i];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PK; ++q) {
+            const int it = tid + q * NT;
+            if (NKL % NT == 0 || it < NKL) {
+                const int jj = it & (TH - 1), rest = it / TH;
+                ks[rest * (TH + 1) + jj] = kr[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PN; ++q) {
+            const int it = tid + q * NT;
+            if (NKN % NT == 0 || it < NKN) ks[it * (TH + 1) + TH] = kn[q];
+        }
+        __syncthreads();
+        if (t + 1 < CPB) {   // in flight during this tile's transforms
+            load_tile(f0 + TH);
+            load_last(f0 + TH);
+        }
+
+        fft_io<NZ, -1, NLN, NT, Rows, true, false, true>(buf, twZ, lds_src, lds_sink);
+        __syncthreads();
+
+        // H^_a = sum_b K_ab M^_b; K folded: ky mirrors flip xy and yz, kz > NZ/2 flips xz and yz
+        constexpr int NP = NZ * NC;
+#pragma unroll
+        for (int it0 = 0; it0 < NP; it0 += NT) {
+            const int it = it0 + tid;
+            if (NP % NT != 0 && it >= NP) break;
+            const int j = it & (NC - 1), kz = it >> LNC;
+            const bool mirror = j >= TH;
+            const int slot = mirror ? NC - j : j;             // f - f0
+            // ky mirrors flip xy and yz, except the Nyquist column (f = Ny/2)
+            const float sy = (mirror && 2 * (f0 + slot) != Ny) ? -1.f : 1.f;
+            const int kzf = 2 * kz > NZ ? NZ - kz : kz;
+            const float sz = 2 * kz > NZ ? -1.f : 1.f;
+            constexpr int KC = KT * (TH + 1);
+            const float* kp = ks + kzf * (TH + 1) + slot;
+            const float kxx = kp[0], kyy = kp[KC], kzz = kp[2 * KC];
+            const float kxy = sy * kp[3 * KC], kxz = sz * kp[4 * KC], kyz = sy * sz * kp[5 * KC];
+            float2* p = buf + j * LS + lpad(kz);
+            const float2 mx = p[0], my = p[NC * LS], mz = p[2 * NC * LS];
+            auto dot3 = [](float a, float x, float bb, float y, float cc, float z) {
+                return fmaf(cc, z, fmaf(bb, y, a * x));
+            };
+            p[0] = make_float2(dot3(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3(kxx, mx.y, kxy, my.y, kxz, mz.y));
+            p[NC * LS] = make_float2(dot3(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3(kxy, mx.y, kyy, my.y, kyz, mz.y));
+            p[2 * NC * LS] = make_float2(dot3(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3(kxz, mx.y, kyz, my.y, kzz, mz.y));
+        }
+        __syncthreads();
+        fft_io<NZ, +1, NLN, NT, Rows, false, true, true>(buf, twZ, lds_src, lds_sink);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PE; ++i) {
+            const int e = tid + i * NT;
+            if (NE % NT == 0 || e < NE) {
+                const int z = (e >> LNC) & (NZH - 1), c = e >> (LNC + LNZH);
+                col[c * cstride + (uint32_t)z * P + ky] = buf[(c * NC + jt) * LS + lpad(z)];
+            }
+        }
+        if (t + 1 < CPB) __syncthreads();  // the stores have read LDS before the next tile is written
+    }
+}
+
 int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, hipStream_t s,
                       bool periodic) {
     if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "z stage: bad batch size");
@@ -157,10 +323,24 @@ int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, h
     {                                                                                          \
         constexpr int TH = ZTile<NZ, V>::TH;                                                   \
         b.start[0] = 0;                                                                        \
+        constexpr int CPB = 2;                                                                 \
+        bool lean = NZ >= 2 && mf == 0 && (2 * TH <= NT);                                      \
+        for (int r = 0; r < b.count; ++r) {                                                    \
+            int ny = b.d[r].Ny > 1 ? b.d[r].Ny / 2 : 1;                                        \
+            lean = lean && b.d[r].Ny >= 2 && (b.d[r].Ny & (b.d[r].Ny - 1)) == 0 &&             \
+                   ny % (CPB * TH) == 0;                                                       \
+        }                                                                                      \
         for (int r = 0; r < b.count; ++r) {                                                    \
             int ny = b.d[r].Ny > 1 ? b.d[r].Ny / 2 : 1;                                        \
             int th = TH < ny ? TH : ny;                                                        \
-            b.start[r + 1] = b.start[r] + ((ny + th - 1) / th) * b.d[r].nk;                   \
+            b.start[r + 1] = b.start[r] + (lean ? ny / (CPB * TH) : (ny + th - 1) / th) * b.d[r].nk; \
+        }                                                                                      \
+        if constexpr (NZ >= 2 && 2 * TH <= NT) {                                               \
+            if (lean) {                                                                        \
+                hipLaunchKernelGGL((z_convolve_lean_kernel<NZ, TH, CPB>),                     \
+                                   dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);   \
+                break;                                                                         \
+            }                                                                                  \
         }                                                                                      \
         DM_MF_DISPATCH(V, hipLaunchKernelGGL((z_convolve_kernel<NZ, TH, MFv>),                \
                            dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)          \
