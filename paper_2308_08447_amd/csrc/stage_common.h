@@ -78,6 +78,12 @@ struct YTile { static constexpr int LPB = 2 * L >= (1024 << V) ? 1 : (1024 << V)
 // z: NZ * TH = 256, 512, 1024
 template <int NZ, int V>
 struct ZTile { static constexpr int TH = (256 << V) / NZ < 1 ? 1 : (256 << V) / NZ; };
+// lean z kernel (512 threads): folded ky per tile = 512 / NZ, x2, x4, within 2 .. 32
+template <int NZ, int V>
+struct LeanZTile {
+    static constexpr int T0 = (512 << V) / NZ;
+    static constexpr int TH = T0 < 2 ? 2 : (T0 > 32 ? 32 : T0);
+};
 
 // Calls f with the MF form as a compile-time constant (0 for variants other than
 // 1): 0 (FP32) or 3 (three-term split BF16 products).

@@ -137,9 +137,12 @@ __global__ __launch_bounds__(NT) void z_convolve_kernel(const ZBatch b,
 // values are loaded into registers while the current tile is transformed.  Per
 // column the arithmetic is that of the kernel above, so both give the same
 // bits.  Requires N_y / 2 to be a multiple of CPB TH.
+constexpr int NTZ = 512;  // threads of the lean z kernel
+
 template <int NZ, int TH, int CPB>
-__global__ __launch_bounds__(NT) void z_convolve_lean_kernel(const ZBatch b,
+__global__ __launch_bounds__(NTZ) void z_convolve_lean_kernel(const ZBatch b,
                                                              const float2* __restrict__ tw_all) {
+    constexpr int NT = NTZ;
     static_assert(NZ >= 2 && (NZ & (NZ - 1)) == 0 && (TH & (TH - 1)) == 0, "powers of two");
     constexpr int NZH = NZ / 2;                  // stored z planes
     constexpr int KT = NZ / 2 + 1;               // folded kz values
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(NT) void z_convolve_lean_kernel(const ZBatch b,
     __shared__ float2 buf[NLN * LS];
     __shared__ float ks[6 * KT * (TH + 1)];      // [comp][kz][f - f0]
     __shared__ float2 twZ[NZ];
-    stage_table(twZ, tw_all + tw_offset(NZ), NZ);
+    for (int i = threadIdx.x; i < NZ; i += NT) twZ[i] = tw_all[tw_offset(NZ) + i];
     const int tid = threadIdx.x;
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
@@ -322,23 +325,24 @@ int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, h
 #define BODY(V)                                                                                \
     {                                                                                          \
         constexpr int TH = ZTile<NZ, V>::TH;                                                   \
+        constexpr int THL = LeanZTile<NZ, V>::TH;                                              \
         b.start[0] = 0;                                                                        \
         constexpr int CPB = 2;                                                                 \
-        bool lean = NZ >= 2 && mf == 0 && (2 * TH <= NT);                                      \
+        bool lean = NZ >= 2 && mf == 0;                                                        \
         for (int r = 0; r < b.count; ++r) {                                                    \
             int ny = b.d[r].Ny > 1 ? b.d[r].Ny / 2 : 1;                                        \
             lean = lean && b.d[r].Ny >= 2 && (b.d[r].Ny & (b.d[r].Ny - 1)) == 0 &&             \
-                   ny % (CPB * TH) == 0;                                                       \
+                   ny % (CPB * THL) == 0;                                                      \
         }                                                                                      \
         for (int r = 0; r < b.count; ++r) {                                                    \
             int ny = b.d[r].Ny > 1 ? b.d[r].Ny / 2 : 1;                                        \
             int th = TH < ny ? TH : ny;                                                        \
-            b.start[r + 1] = b.start[r] + (lean ? ny / (CPB * TH) : (ny + th - 1) / th) * b.d[r].nk; \
+            b.start[r + 1] = b.start[r] + (lean ? ny / (CPB * THL) : (ny + th - 1) / th) * b.d[r].nk; \
         }                                                                                      \
-        if constexpr (NZ >= 2 && 2 * TH <= NT) {                                               \
+        if constexpr (NZ >= 2) {                                                               \
             if (lean) {                                                                        \
-                hipLaunchKernelGGL((z_convolve_lean_kernel<NZ, TH, CPB>),                     \
-                                   dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);   \
+                hipLaunchKernelGGL((z_convolve_lean_kernel<NZ, THL, CPB>),                    \
+                                   dim3((unsigned)finish_batch(b)), dim3(NTZ), 0, s, b, tw);  \
                 break;                                                                         \
             }                                                                                  \
         }                                                                                      \

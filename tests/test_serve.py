@@ -119,6 +119,39 @@ def test_budget_admission_and_oversized_request(gpu_lib):
         pkg.serve_close(srv)
 
 
+@pytest.mark.gpu
+def test_small_request_passes_a_blocked_one(gpu_lib):
+    """Admission scans the queue in arrival order and lets a request that fits
+    pass one that does not: with A running, B (too large to join A) waits, and
+    the small S submitted after B is admitted, finishes first, and equals its
+    alone result bit for bit."""
+    nA, nB, nS = (256, 256, 4), (256, 128, 8), (32, 32, 1)
+
+    def need(n):  # tensor + FFT workspace, four RK4 buffers and m
+        return pkg.demag_plan_bytes(n + CELL) + 60 * n[0] * n[1] * n[2]
+
+    budget = need(nA) + need(nS) + (need(nB) // 2)   # A and S fit together; A and B do not
+    assert budget < need(nA) + need(nB)
+    mA, mB, mS = (W.unit_vectors((n[2], n[1], n[0]), seed=40 + i) for i, n in enumerate((nA, nB, nS)))
+    srv = pkg.serve_open(budget, 8, 0)
+    try:
+        rA = pkg.serve_submit(srv, nA + CELL, _params(0.2), 1e-13, 400, mA)
+        rB = pkg.serve_submit(srv, nB + CELL, _params(0.2), 1e-13, 4, mB)
+        rS = pkg.serve_submit(srv, nS + CELL, _params(0.3), 1e-13, 4, mS)
+        outS = np.empty_like(mS)
+        latS = pkg.serve_wait(srv, rS, outS)
+        latB = pkg.serve_wait(srv, rB, np.empty_like(mB))
+        latA = pkg.serve_wait(srv, rA, np.empty_like(mA))
+        stats = pkg.serve_get_stats(srv)
+    finally:
+        pkg.serve_close(srv)
+    print("latencies A, B, S:", latA, latB, latS, flush=True)
+    assert stats["completed"] == 3 and stats["peak_bytes"] <= budget
+    assert latS < latB        # S did not wait behind B
+    assert latB > latA * 0.5  # B waited for A's memory
+    assert np.array_equal(outS, _alone(nS, 0.3, 4, mS))
+
+
 def test_serve_argument_checks_on_host():
     lib = pkg.load()
     import ctypes
