@@ -299,7 +299,10 @@ int demag_timing_read(demag_plan* plan, double* total_ms, int32_t* launches);
  * Each FFT stage (DEMAG_STAGE_X_FWD .. DEMAG_STAGE_X_INV) has DEMAG_NVARIANTS
  * tile shapes (how many rows, lines or columns one workgroup transforms).  All
  * variants of the five-pass stages produce bit-identical results; they differ
- * only in speed.  In the thin-mesh form (DEMAG_FORM_THIN) the variant of
+ * only in speed.  (At N_z = 64 the five-pass Z_CONV variants 0 and 2 are a
+ * register form of the z convolution with 32 or 64 columns per workgroup and
+ * variant 1 the LDS form; they run the same per-column arithmetic.)  In the
+ * thin-mesh form (DEMAG_FORM_THIN) the variant of
  * X_FWD and X_INV sets the row pairs one workgroup transforms per round (8, 4
  * or 2; 4, 2 or 1 at n_x = 1024), again bit-identical, and the variant of
  * Z_CONV, where n_y >= 256, the y convolution's thread count (radix order) and

@@ -852,13 +852,16 @@ int demag_autotune(demag_plan* plan, void* stream) {
     //    row pairs per round of the two xz kernels and the thread count (radix
     //    order) of the y convolution.
     rc = run_field_single(plan, M, H, 1.0f, s);
+    // Each variant is timed in two rounds (5 launches each) and keeps its faster
+    // round, so one slow round on a busy device does not decide the choice.
     for (int st = 0; st < 5 && !rc && plan->xz; st += 2) {
         const int LNY = 2 * g.ny;
         const int nv = st == 2 ? (LNY >= 512 ? NVARIANTS : 1) : NVARIANTS;
         if (nv < 2) continue;
         double best = 1e30;
         int best_v = plan->variant[st];
-        for (int v = 0; v < nv && !rc; ++v) {
+        for (int vr = 0; vr < 2 * nv && !rc; ++vr) {
+            const int v = vr % nv;
             auto fn = [&]() -> int {
                 switch (st) {
                     case 0: return launch_xz_forward(one(xzdesc(plan, M, H, 1.0f)), g.nx, g.nz, v, plan->tw, s);
@@ -880,7 +883,8 @@ int demag_autotune(demag_plan* plan, void* stream) {
         if ((st == 1 || st == 3) && g.ny == 1) continue;
         double best = 1e30;
         int best_v = plan->variant[st];
-        for (int v = 0; v < NVARIANTS && !rc; ++v) {
+        for (int vr = 0; vr < 2 * NVARIANTS && !rc; ++vr) {
+            const int v = vr % NVARIANTS;
             const int nk = g.ny == 1 ? g.X1 : per;
             auto fn = [&]() -> int {
                 switch (st) {

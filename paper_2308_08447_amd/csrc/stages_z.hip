@@ -294,6 +294,130 @@ __global__ __launch_bounds__(NTZ) void z_convolve_lean_kernel(const ZBatch b,
     }
 }
 
+// Register form of the lean stage for N_z = 64, whose FFT plan above is two
+// radix-8 passes (R = 8).  The last pass of the forward z FFT leaves butterfly j
+// holding X[j + R r] (r < R), and the first pass of the inverse reads exactly
+// those elements, so the thread that runs butterfly j of both passes forms the
+// tensor product of its R frequencies in registers.  Thread (column, j) thus
+// loads its R/2 nonzero inputs z = j + R r of each component from global memory,
+// runs the first forward pass in registers, exchanges once through LDS, runs the
+// last pass, multiplies, runs the first inverse pass, exchanges once more, runs
+// the last inverse pass and stores its R/2 kept outputs: LDS is touched twice per
+// element and direction instead of four or more times, and the tensor values
+// come straight from global memory (each is used by four threads of the block:
+// kz and N_z - kz, ky and its mirror).  Columns are paired as in the lean
+// kernel: CB columns per block, CB/2 folded ky and their aligned mirror run.
+// The exchanges go one component at a time through two alternating LDS slots, so
+// a slot is rewritten only after the barrier that follows its last read.  The
+// per-column arithmetic is that of the two kernels above (same passes, same
+// twiddle table entries, same product), so all three give the same bits.
+// Requires N_y / 2 to be a multiple of CB / 2.
+template <int NZ, int CB>
+__global__ __launch_bounds__(CB * 8, 4) void z_convolve_sq_kernel(const ZBatch b,
+                                                               const float2* __restrict__ tw_all) {
+    constexpr int R = 8;
+    static_assert(NZ == 64 && radix_of(NZ, 0) == R && radix_of(NZ, 1) == R && npasses(NZ) == 2,
+                  "two radix-8 passes");
+    constexpr int NT = CB * R;
+    constexpr int TH = CB / 2;                   // folded ky per block
+    constexpr int RIN = R / 2;                   // nonzero inputs (and kept outputs) per butterfly
+    constexpr int NZH = NZ / 2;
+    __shared__ float2 ex[2][NZ * CB];            // element e of column c at e * CB + c
+    const int tid = threadIdx.x;
+    // with 64 columns per block a wave is one butterfly index j: keep it scalar
+    const int c = tid % CB;
+    const int j = CB == 64 ? __builtin_amdgcn_readfirstlane(tid / CB) : tid / CB;
+    const int gid = xcd_tile(blockIdx.x, gridDim.x);
+    const int item = batch_item(b, gid);
+    const ZDesc& d = b.d[item];
+    const int Ny = d.Ny, Z1 = d.Z1;
+    const int nbt = (Ny >> 1) / TH;              // blocks per kx
+    const int id = gid - b.start[item];
+    const int kl = id / nbt, kx = d.k0 + kl;
+    const int f0 = (id - kl * nbt) * TH;
+    const uint32_t P = (uint32_t)d.xc * (uint32_t)Ny;   // elements per z plane of the chunk
+    const uint32_t cstride = (uint32_t)NZH * P;
+    const bool mirror = c >= TH;
+    const int ky = mirror ? Ny - f0 - CB + c : f0 + c;
+    const int slot = mirror ? CB - c : c;        // folded f - f0
+    const float sy = (mirror && 2 * (f0 + slot) != Ny) ? -1.f : 1.f;
+    // Global accesses are a block-uniform base plus a 32-bit byte offset (the
+    // chunk is at most 128 MB, the tensor below 4 GB).
+    char* __restrict__ sb = reinterpret_cast<char*>(d.S2 + (size_t)kl * Ny);
+    const uint32_t so = ((uint32_t)ky + (uint32_t)j * P) * 8u;
+    auto s2 = [&](int cc, int r) -> float2& {
+        return *reinterpret_cast<float2*>(sb + (so + ((uint32_t)cc * cstride + (uint32_t)(R * r) * P) * 8u));
+    };
+    // tensor value of component q at folded kz: kz = j + R r <= N_z/2 for r < R/2,
+    // else N_z - kz = (N_z - R - R r) + (R - j)
+    const char* __restrict__ kb = reinterpret_cast<const char*>(d.K + (size_t)kx * d.Y1 + f0);
+    const uint32_t kpl = (uint32_t)d.X1 * (uint32_t)d.Y1;
+    const uint32_t klo = ((uint32_t)slot + (uint32_t)j * kpl) * 4u;
+    const uint32_t khi = ((uint32_t)slot + (uint32_t)(R - j) * kpl) * 4u;
+    auto kval = [&](int q, int r) -> float {
+        const uint32_t pl = (uint32_t)q * (uint32_t)Z1 + (uint32_t)(r < RIN ? R * r : NZ - R - R * r);
+        return *reinterpret_cast<const float*>(kb + ((r < RIN ? klo : khi) + pl * kpl * 4u));
+    };
+
+    float2 v[3][R];
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+        for (int r = 0; r < RIN; ++r) v[cc][r] = s2(cc, r);
+    // the last passes' twiddles W^(j 2^d), W = exp(-2 pi i / N_z), as table entries
+    const float2* twz = tw_all + tw_offset(NZ);
+    TwRun twf;
+#pragma unroll
+    for (int dd = 0; (1 << dd) < R; ++dd) twf.p[dd] = twz[j << dd];
+
+    int sl = 0;
+    auto exchange = [&](float2* a) {             // a[r] = element j R + r in, j + R r out
+        float2* e = ex[sl];
+#pragma unroll
+        for (int r = 0; r < R; ++r) e[(j * R + r) * CB + c] = a[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = e[(j + R * r) * CB + c];
+        sl ^= 1;
+    };
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+        dft_half_in<R, -1>(v[cc]);
+        exchange(v[cc]);
+        dft2k<R, -1>(v[cc], twf);
+    }
+    // H^_a = sum_b K_ab M^_b; ky mirrors flip xy and yz (not the Nyquist column),
+    // kz > N_z/2 flips xz and yz
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int kz = j + R * r;
+        const float sz = 2 * kz > NZ ? -1.f : 1.f;
+        float kv[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) kv[q] = kval(q, r);
+        const float kxx = kv[0], kyy = kv[1], kzz = kv[2];
+        const float kxy = sy * kv[3], kxz = sz * kv[4], kyz = sy * sz * kv[5];
+        const float2 mx = v[0][r], my = v[1][r], mz = v[2][r];
+        auto dot3 = [](float a, float x, float bb, float y, float cc2, float z) {
+            return fmaf(cc2, z, fmaf(bb, y, a * x));
+        };
+        v[0][r] = make_float2(dot3(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3(kxx, mx.y, kxy, my.y, kxz, mz.y));
+        v[1][r] = make_float2(dot3(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3(kxy, mx.y, kyy, my.y, kyz, mz.y));
+        v[2][r] = make_float2(dot3(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3(kxz, mx.y, kyz, my.y, kzz, mz.y));
+    }
+    TwRun twi;
+#pragma unroll
+    for (int dd = 0; (1 << dd) < R; ++dd) twi.p[dd] = make_float2(twf.p[dd].x, -twf.p[dd].y);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+        dft<R, +1>(v[cc]);
+        exchange(v[cc]);
+        dft2k<R, +1>(v[cc], twi);
+#pragma unroll
+        for (int r = 0; r < RIN; ++r) s2(cc, r) = v[cc][r];
+    }
+}
+
 int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, hipStream_t s,
                       bool periodic) {
     if (b.count < 1 || b.count > MAXB) return fail(DEMAG_EINVAL, "z stage: bad batch size");
@@ -338,6 +462,21 @@ int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, h
             int ny = b.d[r].Ny > 1 ? b.d[r].Ny / 2 : 1;                                        \
             int th = TH < ny ? TH : ny;                                                        \
             b.start[r + 1] = b.start[r] + (lean ? ny / (CPB * THL) : (ny + th - 1) / th) * b.d[r].nk; \
+        }                                                                                      \
+        if constexpr (NZ == 64) {                                                              \
+            /* variants 0 and 2: the register form with 32 or 64 columns per block */        \
+            constexpr int CBQ = V == 2 ? 64 : 32;                                              \
+            bool sq = V != 1 && mf == 0;                                                       \
+            for (int r = 0; r < b.count; ++r)                                                  \
+                sq = sq && b.d[r].Ny >= 2 && (b.d[r].Ny & (b.d[r].Ny - 1)) == 0 &&             \
+                     (b.d[r].Ny / 2) % (CBQ / 2) == 0;                                         \
+            if (sq) {                                                                          \
+                for (int r = 0; r < b.count; ++r)                                              \
+                    b.start[r + 1] = b.start[r] + (b.d[r].Ny / CBQ) * b.d[r].nk;               \
+                hipLaunchKernelGGL((z_convolve_sq_kernel<NZ, CBQ>), dim3((unsigned)finish_batch(b)), \
+                                   dim3(CBQ * 8), 0, s, b, tw);                                \
+                break;                                                                         \
+            }                                                                                  \
         }                                                                                      \
         if constexpr (NZ >= 2) {                                                               \
             if (lean) {                                                                        \

@@ -261,3 +261,31 @@ def test_full_size_dense_targets(gpu_lib, torch_dev, n, cell):
     assert err <= TOL
     assert worst <= TOL
     assert max(faces.values()) <= TOL
+
+
+def test_large_film_z_variants_bitwise(gpu_lib, torch_dev):
+    """1024x1024x32: the z stage's variants are the register form with 32 and
+    64 columns per block (0, 2) and the lean LDS form (1).  All three run the
+    same per-column arithmetic, so the full field is bitwise the same for each
+    (and for several chunk counts); the default one is checked against the
+    direct sum above."""
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    n = (1024, 1024, 32)
+    _say("z variants bitwise", n)
+    plan = pkg.demag_setup(n + W.CELL_4NM)
+    try:
+        M = torch.from_numpy(W.magnetisation(n, 5)).cuda()
+        ref = torch.empty_like(M)
+        pkg.demag_field(plan, M, ref)
+        for v in range(pkg.NVARIANTS):
+            for nch in (13, 20):
+                pkg.demag_set_variant(plan, 2, v)
+                pkg.demag_set_chunks(plan, nch)
+                H = torch.empty_like(M)
+                pkg.demag_field(plan, M, H)
+                torch.cuda.synchronize()
+                _say("  variant", v, "chunks", nch, "equal", bool(torch.equal(H, ref)))
+                assert torch.equal(H, ref), (v, nch)
+    finally:
+        pkg.demag_destroy(plan)
