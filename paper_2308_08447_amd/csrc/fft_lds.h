@@ -782,6 +782,89 @@ __device__ __forceinline__ void fft_io(float2* buf, TW tw, Src src, Sink sink) {
     }
 }
 
+// The same transform (FP32, at least two passes) split where a caller wants the
+// last pass's outputs in registers: fft_head runs the first and middle passes
+// (src -> LDS, ending with a barrier); fft_tail runs the last pass from LDS and
+// leaves butterfly b = tid + q NT's outputs in v[q][r], r < R, where Addr's
+// split of b into (line, j) gives element j + r L/R.  fft_head then fft_tail
+// does exactly the arithmetic of fft_io (HALF_OUT only drops outputs there).
+template <int L>
+constexpr int tail_radix() { return radix_of(L, npasses(L) - 1); }
+template <int L, int NLINES, int NT>
+constexpr int tail_per() { return (NLINES * (L / tail_radix<L>()) + NT - 1) / NT; }
+
+template <int L, int DIR, int NLINES, int NT, class Addr, bool HALF_IN, bool SYNC_IO, class TW,
+          class Src>
+__device__ __forceinline__ void fft_head(float2* buf, TW tw, Src src) {
+    static_assert(npasses(L) >= 2, "a split transform needs two passes");
+    constexpr int R0 = radix_of(L, 0);
+    first_pass<L, R0, DIR, NLINES, NT, Addr, HALF_IN, SYNC_IO, true>(buf, src);
+    middle_passes<L, 1, R0, DIR, NLINES, NT, Addr, 0>(buf, tw, Dft16Matrix<0>{});
+}
+
+// fft_head with the first pass's inputs already in registers: v[q][r] holds
+// element j + r L/R0 of the line that Addr's split gives butterfly
+// b = tid + q NT (consumed).
+template <int L>
+constexpr int head_radix() { return radix_of(L, 0); }
+template <int L, int NLINES, int NT>
+constexpr int head_per() { return (NLINES * (L / head_radix<L>()) + NT - 1) / NT; }
+
+template <int L, int DIR, int NLINES, int NT, class Addr, class TW>
+__device__ __forceinline__ void fft_head_regs(float2* buf, TW tw,
+                                              float2 (&v)[head_per<L, NLINES, NT>()][head_radix<L>()]) {
+    static_assert(npasses(L) >= 2, "a split transform needs two passes");
+    constexpr int R = head_radix<L>();
+    constexpr int NB = L / R;
+    constexpr int TOT = NB * NLINES;
+    constexpr int PER = head_per<L, NLINES, NT>();
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        int b = tid + q * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            int line, j;
+            Addr::template split<NB>(b, line, j);
+            dft<R, DIR>(v[q]);
+            float2* dst = buf + Addr::idx(line, j * R);
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[Addr::template at<is_pow2c(L)>(j * R, r)] = v[q][r];
+        }
+    }
+    __syncthreads();
+    middle_passes<L, 1, R, DIR, NLINES, NT, Addr, 0>(buf, tw, Dft16Matrix<0>{});
+}
+
+template <int L, int DIR, int NLINES, int NT, class Addr, class TW>
+__device__ __forceinline__ void fft_tail(const float2* buf, TW tw,
+                                         float2 (&v)[tail_per<L, NLINES, NT>()][tail_radix<L>()]) {
+    constexpr int R = tail_radix<L>();
+    constexpr int NB = L / R;
+    constexpr int TOT = NB * NLINES;
+    constexpr int PER = tail_per<L, NLINES, NT>();
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        int b = tid + q * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            int line, j;
+            Addr::template split<NB>(b, line, j);
+            const float2* src = buf + Addr::idx(line, j);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = src[Addr::template at<is_pow2c(L)>(j, r * NB)];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        int b = tid + q * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            int line, j;
+            Addr::template split<NB>(b, line, j);
+            dft_twiddled<R, DIR>(v[q], tw, j);
+        }
+    }
+}
+
 // In-place FFT of NLINES lines of length L in LDS (caller syncs before; the
 // function ends with a barrier).  DIR = -1 forward, +1 inverse (unnormalised).
 // tw points at the length-L table exp(-2 pi i t/L), t < L.

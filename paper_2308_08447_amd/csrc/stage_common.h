@@ -72,6 +72,14 @@ struct XTile {
     static constexpr int CAP = (INV ? 8192 : 16384) / L < 2 ? 2 : (INV ? 8192 : 16384) / L;
     static constexpr int TY = (4 << V) < CAP ? (4 << V) : CAP;
 };
+// x inverse, register form (variants 1 and 2): rows per block 4 and 8, capped so
+// the parked even outputs and the prefetched odd inputs stay within registers
+template <int L, int V>
+struct XRegTile {
+    static constexpr int CAP = 8192 / L < 2 ? 2 : 8192 / L;
+    static constexpr int T0 = V <= 1 ? 4 : 8;
+    static constexpr int TY = T0 < CAP ? T0 : CAP;
+};
 // y: padded elements per block 1024, 2048, 4096 -> lines per block
 template <int L, int V>
 struct YTile { static constexpr int LPB = 2 * L >= (1024 << V) ? 1 : (1024 << V) / (2 * L); };

@@ -98,6 +98,101 @@ __global__ __launch_bounds__(NT) void x_forward_kernel(const XBatch b,
     }
 }
 
+// Register form of the forward (FP32, open x, power-of-two L >= 32): the row
+// values the first pass of the even part reads stay in registers and feed the
+// first pass of the odd part as well, so M is read from global memory once
+// instead of twice.  The arithmetic is that of x_forward_kernel (the odd inputs
+// are the same products z[t] W_2L^t), so both give the same bits.
+template <int L, int TY>
+__global__ __launch_bounds__(NT) void x_forward_reg_kernel(const XBatch b,
+                                                           const float2* __restrict__ tw_all) {
+    constexpr int X1 = L + 1;
+    constexpr int NP = TY / 2;
+    constexpr int LS = lpad_c(L) + 1;
+    __shared__ float2 buf[NP * LS];
+    __shared__ float2 twt[x_tw2<L, 0>() ? tw2_entries(L) : L];
+    const auto twL = x_twiddles<L, 0>(twt, tw_all + tw_offset(L));
+    const float2* tw2L = tw_all + tw_offset(2 * L);
+    const int tid = threadIdx.x;
+    const int gid = xcd_tile(blockIdx.x, gridDim.x);
+    const int item = batch_item(b, gid);
+    const float* __restrict__ M = b.d[item].M;
+    float2* __restrict__ S1 = b.d[item].S1;
+    const int ny = b.d[item].ny, nz = b.d[item].nz;
+    const float scale = b.d[item].scale;
+    const int nyt = (ny + TY - 1) / TY;
+    const int id = gid - b.start[item];
+    const int y0 = (id % nyt) * TY, z = (id / nyt) % nz, c = id / (nyt * nz);
+    const int rows = min(TY, ny - y0);
+    const float* src = M + ((size_t)(c * nz + z) * ny + y0) * L;
+    float2* dst = S1 + (size_t)(c * nz + z) * X1 * ny + y0;
+    using Rows = RowLines<LS>;
+    constexpr int R0 = head_radix<L>(), PF = head_per<L, NP, NT>(), NB0 = L / R0;
+
+    float2 raw[PF][R0];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        const int bb = tid + q * NT;
+        if ((NB0 * NP) % NT == 0 || bb < NB0 * NP) {
+            int p, j;
+            Rows::template split<NB0>(bb, p, j);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                const int t = j + r * NB0;
+                const float a = (2 * p < rows) ? src[(size_t)(2 * p) * L + t] : 0.f;
+                const float bv = (2 * p + 1 < rows) ? src[(size_t)(2 * p + 1) * L + t] : 0.f;
+                raw[q][r] = make_float2(a * scale, bv * scale);
+            }
+        }
+    }
+    auto to_lds = [&](int p, int k, float2 v) { buf[p * LS + lpad(k)] = v; };
+    {
+        float2 v[PF][R0];
+#pragma unroll
+        for (int q = 0; q < PF; ++q)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) v[q][r] = raw[q][r];
+        fft_head_regs<L, -1, NP, NT, Rows>(buf, twL, v);
+        last_pass<L, tail_radix<L>(), -1, NP, NT, Rows, false, true>(buf, twL, to_lds);
+    }
+    __syncthreads();
+    // even frequencies kx = 2m, m = 0..L/2: Z[2m] = E[m], Z[2L-2m] = E[(L-m) mod L]
+    for (int it = tid; it < (L / 2 + 1) * NP; it += NT) {
+        int p = it % NP, m = it / NP;
+        float2 Zk = buf[p * LS + lpad(m)];
+        float2 Zn = cconj(buf[p * LS + lpad(m == 0 ? 0 : L - m)]);
+        float2 Xa = cscale(cadd(Zk, Zn), 0.5f);
+        float2 d = csub(Zk, Zn);
+        float2 Xb = make_float2(0.5f * d.y, -0.5f * d.x);
+        store_pair(dst + (size_t)(2 * m) * ny + 2 * p, Xa, Xb, rows - 2 * p);
+    }
+    __syncthreads();
+    {
+        float2 v[PF][R0];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int bb = tid + q * NT;
+            int p, j;
+            Rows::template split<NB0>(bb, p, j);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) v[q][r] = cmul(raw[q][r], tw2L[j + r * NB0]);
+        }
+        fft_head_regs<L, -1, NP, NT, Rows>(buf, twL, v);
+        last_pass<L, tail_radix<L>(), -1, NP, NT, Rows, false, true>(buf, twL, to_lds);
+    }
+    __syncthreads();
+    // odd frequencies kx = 2m+1, m < L/2: Z[2m+1] = O[m], Z[2L-2m-1] = O[L-1-m]
+    for (int it = tid; it < (L / 2) * NP; it += NT) {
+        int p = it % NP, m = it / NP;
+        float2 Zk = buf[p * LS + lpad(m)];
+        float2 Zn = cconj(buf[p * LS + lpad(L - 1 - m)]);
+        float2 Xa = cscale(cadd(Zk, Zn), 0.5f);
+        float2 d = csub(Zk, Zn);
+        float2 Xb = make_float2(0.5f * d.y, -0.5f * d.x);
+        store_pair(dst + (size_t)(2 * m + 1) * ny + 2 * p, Xa, Xb, rows - 2 * p);
+    }
+}
+
 // Inverse: the even (odd) inputs Z[2m] (Z[2m+1]) of the packed pair are gathered
 // from S1 (consecutive threads, consecutive y) into LDS; the inverse of the even
 // part is parked in a second LDS region, and the last pass of the odd part
@@ -171,6 +266,101 @@ __global__ __launch_bounds__(NT) void x_inverse_kernel(const XBatch b,
         if (2 * p + 1 < rows) dst[(size_t)(2 * p + 1) * L + t] = zz.y;
     };
     fft_io<L, +1, NP, NT, Rows, false, false, true, MF>(buf, twL, from_lds, combine);
+}
+
+// Register form of the inverse (FP32, open x, power-of-two L >= 32): the last
+// pass of the even part leaves IE in the registers of the thread that later runs
+// the same butterfly of the odd part's last pass, so IE needs no second LDS
+// region (half the LDS of the kernel above, twice the blocks per compute unit),
+// and the odd inputs are loaded into registers while the even part is
+// transformed.  The arithmetic is that of x_inverse_kernel, so both give the
+// same bits.
+template <int L, int TY>
+__global__ __launch_bounds__(NT) void x_inverse_reg_kernel(const XBatch b,
+                                                           const float2* __restrict__ tw_all) {
+    constexpr int X1 = L + 1;
+    constexpr int NP = TY / 2;
+    constexpr int LS = lpad_c(L) + 1;
+    __shared__ float2 buf[NP * LS];
+    __shared__ float2 twt[x_tw2<L, 0>() ? tw2_entries(L) : L];
+    __shared__ float2 tw2t[x_tw2<L, 0>() ? tw2_entries(2 * L) : L];
+    const auto twL = x_twiddles<L, 0>(twt, tw_all + tw_offset(L));
+    const auto tw2L = x_twiddles_2l<L, 0, false>(tw2t, tw_all + tw_offset(2 * L));
+    const int tid = threadIdx.x;
+    const int gid = xcd_tile(blockIdx.x, gridDim.x);
+    const int item = batch_item(b, gid);
+    const float2* __restrict__ S1 = b.d[item].S1;
+    float* __restrict__ H = b.d[item].H;
+    const int ny = b.d[item].ny, nz = b.d[item].nz;
+    const int nyt = (ny + TY - 1) / TY;
+    const int id = gid - b.start[item];
+    const int y0 = (id % nyt) * TY, z = (id / nyt) % nz, c = id / (nyt * nz);
+    const int rows = min(TY, ny - y0);
+    const float2* src = S1 + (size_t)(c * nz + z) * X1 * ny + y0;
+    float* dst = H + ((size_t)(c * nz + z) * ny + y0) * L;
+    using Rows = RowLines<LS>;
+
+    for (int it = tid; it < (L / 2 + 1) * NP; it += NT) {
+        int p = it % NP, m = it / NP, kx = 2 * m;
+        float2 Xa, Xb;
+        load_pair(src + (size_t)kx * ny + 2 * p, Xa, Xb, rows - 2 * p);
+        if (m == 0 || 2 * m == L) {
+            Xa.y = 0.f;
+            Xb.y = 0.f;
+        }
+        buf[p * LS + lpad(m)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
+        if (m > 0 && 2 * m < L) buf[p * LS + lpad(L - m)] = make_float2(Xa.x + Xb.y, Xb.x - Xa.y);
+    }
+    // odd inputs kx = 2m + 1, in flight during the even part's transform
+    constexpr int NO = (L / 2) * NP;
+    constexpr int PO = (NO + NT - 1) / NT;
+    float2 oa[PO], ob[PO];
+#pragma unroll
+    for (int q = 0; q < PO; ++q) {
+        const int it = tid + q * NT;
+        if (NO % NT == 0 || it < NO) {
+            const int p = it % NP, m = it / NP;
+            load_pair(src + (size_t)(2 * m + 1) * ny + 2 * p, oa[q], ob[q], rows - 2 * p);
+        }
+    }
+    __syncthreads();
+    auto from_lds = [&](int p, int t) { return buf[p * LS + lpad(t)]; };
+    constexpr int RL = tail_radix<L>(), PER = tail_per<L, NP, NT>(), NB = L / RL;
+    float2 ie[PER][RL];
+    fft_head<L, +1, NP, NT, Rows, false, true>(buf, twL, from_lds);
+    fft_tail<L, +1, NP, NT, Rows>(buf, twL, ie);
+    __syncthreads();
+    // Z[2m+1] at slot m, and Z[2L-2m-1] = conj -> slot L-1-m
+#pragma unroll
+    for (int q = 0; q < PO; ++q) {
+        const int it = tid + q * NT;
+        if (NO % NT == 0 || it < NO) {
+            const int p = it % NP, m = it / NP;
+            const float2 Xa = oa[q], Xb = ob[q];
+            buf[p * LS + lpad(m)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
+            buf[p * LS + lpad(L - 1 - m)] = make_float2(Xa.x + Xb.y, Xb.x - Xa.y);
+        }
+    }
+    __syncthreads();
+    float2 io[PER][RL];
+    fft_head<L, +1, NP, NT, Rows, false, true>(buf, twL, from_lds);
+    fft_tail<L, +1, NP, NT, Rows>(buf, twL, io);
+    // z[t] = IE[t] + W_2L^-t IO[t]; both rows of the pair go straight to H
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int bb = tid + q * NT;
+        if ((NB * NP) % NT == 0 || bb < NB * NP) {
+            int p, j;
+            Rows::template split<NB>(bb, p, j);
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int t = j + r * NB;
+                const float2 zz = cmad(cconj(tw2L[t]), io[q][r], ie[q][r]);
+                if (2 * p < rows) dst[(size_t)(2 * p) * L + t] = zz.x;
+                if (2 * p + 1 < rows) dst[(size_t)(2 * p + 1) * L + t] = zz.y;
+            }
+        }
+    }
 }
 
 // nx == 1: no x transform (N_x = 1); S1[c][z][0][y] = M[c][z][y][0]
@@ -247,6 +437,13 @@ int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hi
         b.start[0] = 0;                                                                       \
         for (int r = 0; r < b.count; ++r)                                                     \
             b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;       \
+        if constexpr (npasses(L) >= 2) {                                                      \
+            if (mf == 0) {                                                                    \
+                hipLaunchKernelGGL((x_forward_reg_kernel<L, TY>),                             \
+                                   dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);   \
+                break;                                                                        \
+            }                                                                                 \
+        }                                                                                     \
         DM_MF_DISPATCH(V, hipLaunchKernelGGL((x_forward_kernel<L, TY, MFv>),                  \
                            dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)          \
     }
@@ -323,9 +520,19 @@ int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hi
 #define BODY(V)                                                                               \
     {                                                                                         \
         constexpr int TY = XTile<L, V, true>::TY;                                             \
+        constexpr int TYR = XRegTile<L, V>::TY;                                               \
+        const bool reg = V >= 1 && mf == 0 && npasses(L) >= 2;                                \
+        const int ty = reg ? TYR : TY;                                                        \
         b.start[0] = 0;                                                                       \
         for (int r = 0; r < b.count; ++r)                                                     \
-            b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;       \
+            b.start[r + 1] = b.start[r] + ((b.d[r].ny + ty - 1) / ty) * b.d[r].nz * 3;       \
+        if constexpr (V >= 1 && npasses(L) >= 2) {                                            \
+            if (reg) {                                                                        \
+                hipLaunchKernelGGL((x_inverse_reg_kernel<L, TYR>),                            \
+                                   dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);   \
+                break;                                                                        \
+            }                                                                                 \
+        }                                                                                     \
         DM_MF_DISPATCH(V, hipLaunchKernelGGL((x_inverse_kernel<L, TY, MFv>),                  \
                            dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)          \
     }
