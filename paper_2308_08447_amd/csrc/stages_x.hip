@@ -274,9 +274,10 @@ __global__ __launch_bounds__(NT) void x_inverse_kernel(const XBatch b,
 // region (half the LDS of the kernel above, twice the blocks per compute unit),
 // and the odd inputs are loaded into registers while the even part is
 // transformed.  The arithmetic is that of x_inverse_kernel, so both give the
-// same bits.
+// same bits.  Registers are held to 128 so that four blocks share a compute
+// unit, as many as the LDS of 8 rows of 1024 allows.
 template <int L, int TY>
-__global__ __launch_bounds__(NT) void x_inverse_reg_kernel(const XBatch b,
+__global__ __launch_bounds__(NT, 4) void x_inverse_reg_kernel(const XBatch b,
                                                            const float2* __restrict__ tw_all) {
     constexpr int X1 = L + 1;
     constexpr int NP = TY / 2;
