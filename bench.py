@@ -32,26 +32,32 @@ import numpy as np
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 ROOT = os.path.dirname(os.path.abspath(__file__))
 # sources whose change invalidates a stored hardware-counter measurement
-KERNEL_SOURCES = ["paper_2308_08447_amd/csrc/" + f for f in (
-    "stages_x.hip", "stages_y.hip", "stages_z.hip", "stages_xz.hip", "stage_common.h", "fft_lds.h",
-    "mfma_dft.h", "engine.h", "dynamics.hip")]
+# kernel sources behind each form's stored counters (a change to one of them
+# invalidates that form's traffic lines)
+_SHARED_SOURCES = ("stage_common.h", "fft_lds.h", "mfma_dft.h", "engine.h")
+KERNEL_SOURCES = {
+    5: ["paper_2308_08447_amd/csrc/" + f
+        for f in ("stages_x.hip", "stages_y.hip", "stages_z.hip") + _SHARED_SOURCES],
+    3: ["paper_2308_08447_amd/csrc/" + f for f in ("stages_xz.hip", "dynamics.hip") + _SHARED_SOURCES],
+}
 COUNTERS = "profiles/counters_thin_film_512x512x16.md"
 COUNTERS_LARGE = "profiles/counters_large_film_1024x1024x32.md"
 
 
-def kernel_sources_sha256():
+def kernel_sources_sha256(form):
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_SOURCES[form]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def counter_traffic(stage, counters=COUNTERS):
+def counter_traffic(stage, counters=COUNTERS, form=3):
     """HBM bytes per launch of `stage` from the stored rocprofv3 counter runs
     (FETCH_SIZE x its copy-kernel calibration + WRITE_SIZE), or None when no
-    measurement is stored or the kernel sources changed since it was taken."""
+    measurement is stored or the form's kernel sources changed since it was
+    taken."""
     path = os.path.join(ROOT, counters)
     if not os.path.exists(path):
         return None
@@ -63,7 +69,7 @@ def counter_traffic(stage, counters=COUNTERS):
                 vals[p[1]] = float(p[2])
             elif len(p) == 2 and p[0] == "kernel_sources_sha256":
                 sha = p[1]
-    if sha != kernel_sources_sha256():
+    if sha != kernel_sources_sha256(form):
         return None
     return vals.get(stage)
 
@@ -317,7 +323,7 @@ def large_film_bench(pkg, args):
     fp = modes["fp32"]
     per_stage = fp["stages"]
     dom = max(per_stage, key=lambda k: per_stage[k]["avg_us"] * per_stage[k]["launches"])
-    tr = [counter_traffic(k, COUNTERS_LARGE) for k in per_stage]
+    tr = [counter_traffic(k, COUNTERS_LARGE, 5) for k in per_stage]
     fp["counter_bytes_per_eval"] = (int(sum(t * per_stage[k]["launches"] / args.steps
                                             for k, t in zip(per_stage, tr)))
                                     if all(t is not None for t in tr) else None)
@@ -331,7 +337,7 @@ def large_film_bench(pkg, args):
            "roofline": {"bound": "hbm", "kernel": dom, "achieved": per_stage[dom]["GB_per_s"],
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(per_stage[dom]["GB_per_s"] / HBM_PEAK_GBS, 4),
-                        "traffic": counter_traffic(dom, COUNTERS_LARGE),
+                        "traffic": counter_traffic(dom, COUNTERS_LARGE, 5),
                         "bytes_per_launch": per_stage[dom]["bytes_per_launch"]},
            "demag_field_bytes_b5": b5,
            "modes": modes}
@@ -592,7 +598,7 @@ def thin_film_block(pkg, args):
     b_form = sum(v for k, v in nbytes.items() if k != "llg")
     # counter-measured HBM bytes of one evaluation (stored rocprofv3 runs of the
     # current kernels), to set against B5
-    tr = [counter_traffic(k) for k in nbytes if k != "llg"]
+    tr = [counter_traffic(k, COUNTERS, form) for k in nbytes if k != "llg"]
     counter_eval = int(sum(tr)) if tr and all(v is not None for v in tr) else None
 
     out = {
@@ -614,7 +620,7 @@ def thin_film_block(pkg, args):
                    "stage_variants": variants, "yz_chunks": nch},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": counter_traffic(dom),
+                     "traffic": counter_traffic(dom, COUNTERS, form),
                      "bytes_per_launch": per_stage[dom]["bytes_per_launch"]},
         "stages": per_stage,
         "demag_field_gcells_per_s": round(cells / t_field / 1e9, 3),
