@@ -53,11 +53,13 @@ def kernel_sources_sha256(form):
     return h.hexdigest()
 
 
-def counter_traffic(stage, counters=COUNTERS, form=3):
+def counter_traffic(stage, counters=COUNTERS, form=3, launches_per_eval=1):
     """HBM bytes per launch of `stage` from the stored rocprofv3 counter runs
-    (FETCH_SIZE x its copy-kernel calibration + WRITE_SIZE), or None when no
-    measurement is stored or the form's kernel sources changed since it was
-    taken."""
+    (FETCH_SIZE x its copy-kernel calibration + WRITE_SIZE): the stage's bytes
+    per evaluation divided by its launches per evaluation in this run (the y
+    and z stages of a chunked plan split one evaluation's bytes over their
+    chunks), or None when no measurement is stored or the form's kernel sources
+    changed since it was taken."""
     path = os.path.join(ROOT, counters)
     if not os.path.exists(path):
         return None
@@ -65,13 +67,13 @@ def counter_traffic(stage, counters=COUNTERS, form=3):
     with open(path) as f:
         for line in f:
             p = line.split()
-            if len(p) == 3 and p[0] == "traffic_bytes_per_launch":
+            if len(p) == 3 and p[0] == "traffic_bytes_per_eval":
                 vals[p[1]] = float(p[2])
             elif len(p) == 2 and p[0] == "kernel_sources_sha256":
                 sha = p[1]
-    if sha != kernel_sources_sha256(form):
+    if sha != kernel_sources_sha256(form) or stage not in vals:
         return None
-    return vals.get(stage)
+    return vals[stage] / launches_per_eval
 
 
 def geometry(n, pbc=(False, False, False)):
@@ -323,10 +325,9 @@ def large_film_bench(pkg, args):
     fp = modes["fp32"]
     per_stage = fp["stages"]
     dom = max(per_stage, key=lambda k: per_stage[k]["avg_us"] * per_stage[k]["launches"])
-    tr = [counter_traffic(k, COUNTERS_LARGE, 5) for k in per_stage]
-    fp["counter_bytes_per_eval"] = (int(sum(t * per_stage[k]["launches"] / args.steps
-                                            for k, t in zip(per_stage, tr)))
-                                    if all(t is not None for t in tr) else None)
+    lpe = {k: per_stage[k]["launches"] / args.steps for k in per_stage}   # launches per evaluation
+    tr = [counter_traffic(k, COUNTERS_LARGE, 5) for k in per_stage]         # per evaluation
+    fp["counter_bytes_per_eval"] = int(sum(tr)) if all(t is not None for t in tr) else None
     out = {"metric": "demag H_d evals: Gcells/s + % HBM roofline; serve p50/p99 latency",
            "value": fp["Gcells_per_s"],
            "unit": "Gcells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -337,7 +338,7 @@ def large_film_bench(pkg, args):
            "roofline": {"bound": "hbm", "kernel": dom, "achieved": per_stage[dom]["GB_per_s"],
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(per_stage[dom]["GB_per_s"] / HBM_PEAK_GBS, 4),
-                        "traffic": counter_traffic(dom, COUNTERS_LARGE, 5),
+                        "traffic": counter_traffic(dom, COUNTERS_LARGE, 5, lpe[dom]),
                         "bytes_per_launch": per_stage[dom]["bytes_per_launch"]},
            "demag_field_bytes_b5": b5,
            "modes": modes}
@@ -598,7 +599,7 @@ def thin_film_block(pkg, args):
     b_form = sum(v for k, v in nbytes.items() if k != "llg")
     # counter-measured HBM bytes of one evaluation (stored rocprofv3 runs of the
     # current kernels), to set against B5
-    tr = [counter_traffic(k, COUNTERS, form) for k in nbytes if k != "llg"]
+    tr = [counter_traffic(k, COUNTERS, form) for k in nbytes if k != "llg"]   # per evaluation
     counter_eval = int(sum(tr)) if tr and all(v is not None for v in tr) else None
 
     out = {
@@ -620,7 +621,8 @@ def thin_film_block(pkg, args):
                    "stage_variants": variants, "yz_chunks": nch},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": counter_traffic(dom, COUNTERS, form),
+                     "traffic": counter_traffic(dom, COUNTERS, form,
+                                                per_stage[dom]["launches"] / evals),
                      "bytes_per_launch": per_stage[dom]["bytes_per_launch"]},
         "stages": per_stage,
         "demag_field_gcells_per_s": round(cells / t_field / 1e9, 3),

@@ -904,12 +904,15 @@ int demag_autotune(demag_plan* plan, void* stream) {
         }
         plan->variant[st] = best_v;
     }
-    // 2. number of chunks, timing the whole evaluation
+    // 2. number of chunks, timing the whole evaluation (each count in two rounds)
     if (!rc && g.ny > 1 && !plan->xz) {
         const int nmin = (g.X1 + plan->xc - 1) / plan->xc;
         double best = 1e30;
         int best_n = plan->nch;
-        for (int n = nmin; n <= 8 * nmin && n <= g.X1 && !rc; n *= 2) {
+        std::vector<int> counts;
+        for (int n = nmin; n <= 8 * nmin && n <= g.X1; n *= 2) counts.push_back(n);
+        for (size_t k = 0; k < 2 * counts.size() && !rc; ++k) {
+            const int n = counts[k % counts.size()];
             plan->nch = n;
             double ms = 0.0;
             rc = time_it([&]() { return run_field_single(plan, M, H, 1.0f, s); }, 3, &ms);

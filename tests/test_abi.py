@@ -69,7 +69,15 @@ def test_plan_bytes_formula():
     nx, ny, nz = 512, 512, 32
     X1, Y1, Z1 = nx + 1, ny + 1, nz + 1
     plane = 3 * nz * 2 * ny * 8                  # one kx plane of the y/z spectra
-    planes = min(X1, (128 << 20) // plane)       # the chunk buffer is capped at 128 MB
+    planes = min(X1, (128 << 20) // plane)       # a chunk buffer is capped at 128 MB
+    expect = 6 * Z1 * X1 * Y1 * 4 + 3 * nz * X1 * ny * 8 + planes * plane
+    assert pkg.demag_plan_bytes((nx, ny, nz, 4e-9, 4e-9, 4e-9)) == expect
+    # 1024x1024x32 needs 13 chunks: the buffer holds 128 MB of kx planes
+    nx, ny, nz = 1024, 1024, 32
+    X1, Y1, Z1 = nx + 1, ny + 1, nz + 1
+    plane = 3 * nz * 2 * ny * 8
+    planes = (128 << 20) // plane
+    assert planes < X1
     expect = 6 * Z1 * X1 * Y1 * 4 + 3 * nz * X1 * ny * 8 + planes * plane
     assert pkg.demag_plan_bytes((nx, ny, nz, 4e-9, 4e-9, 4e-9)) == expect
     # the MFMA forms always take the five-pass form

@@ -267,8 +267,8 @@ def test_large_film_z_variants_bitwise(gpu_lib, torch_dev):
     """1024x1024x32: the z stage's variants are the register form with 32 and
     64 columns per block (0, 2) and the lean LDS form (1).  All three run the
     same per-column arithmetic, so the full field is bitwise the same for each
-    (and for several chunk counts); the default one is checked against the
-    direct sum above."""
+    (and for several chunk counts, and with per-stage timing events on); the
+    default one is checked against the direct sum above."""
     import paper_2308_08447_amd as pkg
     torch = torch_dev
     n = (1024, 1024, 32)
@@ -287,5 +287,38 @@ def test_large_film_z_variants_bitwise(gpu_lib, torch_dev):
                 torch.cuda.synchronize()
                 _say("  variant", v, "chunks", nch, "equal", bool(torch.equal(H, ref)))
                 assert torch.equal(H, ref), (v, nch)
+        # per-stage timing events around every launch leave the result alone
+        pkg.demag_timing_enable(plan, 64)
+        H = torch.empty_like(M)
+        pkg.demag_field(plan, M, H)
+        torch.cuda.synchronize()
+        pkg.demag_timing_enable(plan, 0)
+        assert torch.equal(H, ref)
+    finally:
+        pkg.demag_destroy(plan)
+
+
+def test_large_film_llg_graph_replay_chunked(gpu_lib, torch_dev):
+    """1024x1024x32 takes 13 or more chunks per H_d (39 or more y/z launches).
+    llg_step with nsteps = 2 captures one RK4 step as a HIP graph and replays
+    it: bitwise the result of two eager steps, after a chunk-count change too."""
+    import paper_2308_08447_amd as pkg
+    from oracle import llg as ollg
+    torch = torch_dev
+    n = (1024, 1024, 32)
+    _say("llg graph replay, chunked", n)
+    m0 = torch.from_numpy(W.unit_vectors((n[2], n[1], n[0]), seed=29)).cuda()
+    prm = (W.MS, W.A_EX, 0.1, ollg.GAMMA, (1e4, 0.0, -1e4))
+    plan = pkg.demag_setup(n + W.CELL_4NM)
+    try:
+        for nch in (pkg.demag_get_chunks(plan), 20):
+            pkg.demag_set_chunks(plan, nch)
+            eager, graph = m0.clone(), m0.clone()
+            for _ in range(2):
+                pkg.llg_step(plan, eager, prm, 1e-13, 1)
+            pkg.llg_step(plan, graph, prm, 1e-13, 2)
+            torch.cuda.synchronize()
+            _say("  chunks", nch, "equal", bool(torch.equal(eager, graph)))
+            assert torch.equal(eager, graph), nch
     finally:
         pkg.demag_destroy(plan)
