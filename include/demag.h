@@ -301,7 +301,8 @@ int demag_timing_read(demag_plan* plan, double* total_ms, int32_t* launches);
  * variants of the five-pass stages produce bit-identical results; they differ
  * only in speed.  (At N_z = 64 the five-pass Z_CONV variants 0 and 2 are a
  * register form of the z convolution with 32 or 64 columns per workgroup and
- * variant 1 the LDS form; they run the same per-column arithmetic.)  In the
+ * variant 1 the LDS form; they run the same per-column arithmetic.  For long x
+ * rows, X_FWD variant 0 takes variant 2's rows on twice the threads.)  In the
  * thin-mesh form (DEMAG_FORM_THIN) the variant of
  * X_FWD and X_INV sets the row pairs one workgroup transforms per round (8, 4
  * or 2; 4, 2 or 1 at n_x = 1024), again bit-identical, and the variant of

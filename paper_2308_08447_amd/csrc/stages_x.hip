@@ -9,22 +9,23 @@ namespace dm {
 // tables: the extra product raised their registers past two waves per SIMD.)
 template <int L, int MF>
 constexpr bool x_tw2() { return L >= 1024 && MF == 0; }
-template <int L, int MF>
+template <int L, int MF, int NTX = NT>
 __device__ __forceinline__ auto x_twiddles(float2* twt, const float2* __restrict__ full) {
     if constexpr (x_tw2<L, MF>()) {
-        return stage_tw2<L, NT>(twt, full);
+        return stage_tw2<L, NTX>(twt, full);
     } else {
-        stage_table(twt, full, L);
+        for (int i = threadIdx.x; i < L; i += NTX) twt[i] = full[i];
         return (const float2*)twt;
     }
 }
 // entries t < L of the length-2L table (the inverse's odd-part rotation)
-template <int L, int MF, bool PX>
+template <int L, int MF, bool PX, int NTX = NT>
 __device__ __forceinline__ auto x_twiddles_2l(float2* twt, const float2* __restrict__ full) {
     if constexpr (x_tw2<L, MF>()) {
-        return stage_tw2<2 * L, NT>(twt, full);
+        return stage_tw2<2 * L, NTX>(twt, full);
     } else {
-        if constexpr (!PX) stage_table(twt, full, L);
+        if constexpr (!PX)
+            for (int i = threadIdx.x; i < L; i += NTX) twt[i] = full[i];
         return (const float2*)twt;
     }
 }
@@ -102,16 +103,18 @@ __global__ __launch_bounds__(NT) void x_forward_kernel(const XBatch b,
 // values the first pass of the even part reads stay in registers and feed the
 // first pass of the odd part as well, so M is read from global memory once
 // instead of twice.  The arithmetic is that of x_forward_kernel (the odd inputs
-// are the same products z[t] W_2L^t), so both give the same bits.
-template <int L, int TY>
-__global__ __launch_bounds__(NT) void x_forward_reg_kernel(const XBatch b,
+// are the same products z[t] W_2L^t), so both give the same bits.  NTX threads
+// per block: 512 gives a 16-row tile of 1024 twice the waves of 256 for the
+// same LDS (its 70 KB allow two blocks per compute unit).
+template <int L, int TY, int NTX = NT>
+__global__ __launch_bounds__(NTX) void x_forward_reg_kernel(const XBatch b,
                                                            const float2* __restrict__ tw_all) {
     constexpr int X1 = L + 1;
     constexpr int NP = TY / 2;
     constexpr int LS = lpad_c(L) + 1;
     __shared__ float2 buf[NP * LS];
     __shared__ float2 twt[x_tw2<L, 0>() ? tw2_entries(L) : L];
-    const auto twL = x_twiddles<L, 0>(twt, tw_all + tw_offset(L));
+    const auto twL = x_twiddles<L, 0, NTX>(twt, tw_all + tw_offset(L));
     const float2* tw2L = tw_all + tw_offset(2 * L);
     const int tid = threadIdx.x;
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
@@ -127,13 +130,13 @@ __global__ __launch_bounds__(NT) void x_forward_reg_kernel(const XBatch b,
     const float* src = M + ((size_t)(c * nz + z) * ny + y0) * L;
     float2* dst = S1 + (size_t)(c * nz + z) * X1 * ny + y0;
     using Rows = RowLines<LS>;
-    constexpr int R0 = head_radix<L>(), PF = head_per<L, NP, NT>(), NB0 = L / R0;
+    constexpr int R0 = head_radix<L>(), PF = head_per<L, NP, NTX>(), NB0 = L / R0;
 
     float2 raw[PF][R0];
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
-        const int bb = tid + q * NT;
-        if ((NB0 * NP) % NT == 0 || bb < NB0 * NP) {
+        const int bb = tid + q * NTX;
+        if ((NB0 * NP) % NTX == 0 || bb < NB0 * NP) {
             int p, j;
             Rows::template split<NB0>(bb, p, j);
 #pragma unroll
@@ -152,12 +155,12 @@ __global__ __launch_bounds__(NT) void x_forward_reg_kernel(const XBatch b,
         for (int q = 0; q < PF; ++q)
 #pragma unroll
             for (int r = 0; r < R0; ++r) v[q][r] = raw[q][r];
-        fft_head_regs<L, -1, NP, NT, Rows>(buf, twL, v);
-        last_pass<L, tail_radix<L>(), -1, NP, NT, Rows, false, true>(buf, twL, to_lds);
+        fft_head_regs<L, -1, NP, NTX, Rows>(buf, twL, v);
+        last_pass<L, tail_radix<L>(), -1, NP, NTX, Rows, false, true>(buf, twL, to_lds);
     }
     __syncthreads();
     // even frequencies kx = 2m, m = 0..L/2: Z[2m] = E[m], Z[2L-2m] = E[(L-m) mod L]
-    for (int it = tid; it < (L / 2 + 1) * NP; it += NT) {
+    for (int it = tid; it < (L / 2 + 1) * NP; it += NTX) {
         int p = it % NP, m = it / NP;
         float2 Zk = buf[p * LS + lpad(m)];
         float2 Zn = cconj(buf[p * LS + lpad(m == 0 ? 0 : L - m)]);
@@ -171,18 +174,18 @@ __global__ __launch_bounds__(NT) void x_forward_reg_kernel(const XBatch b,
         float2 v[PF][R0];
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
-            const int bb = tid + q * NT;
+            const int bb = tid + q * NTX;
             int p, j;
             Rows::template split<NB0>(bb, p, j);
 #pragma unroll
             for (int r = 0; r < R0; ++r) v[q][r] = cmul(raw[q][r], tw2L[j + r * NB0]);
         }
-        fft_head_regs<L, -1, NP, NT, Rows>(buf, twL, v);
-        last_pass<L, tail_radix<L>(), -1, NP, NT, Rows, false, true>(buf, twL, to_lds);
+        fft_head_regs<L, -1, NP, NTX, Rows>(buf, twL, v);
+        last_pass<L, tail_radix<L>(), -1, NP, NTX, Rows, false, true>(buf, twL, to_lds);
     }
     __syncthreads();
     // odd frequencies kx = 2m+1, m < L/2: Z[2m+1] = O[m], Z[2L-2m-1] = O[L-1-m]
-    for (int it = tid; it < (L / 2) * NP; it += NT) {
+    for (int it = tid; it < (L / 2) * NP; it += NTX) {
         int p = it % NP, m = it / NP;
         float2 Zk = buf[p * LS + lpad(m)];
         float2 Zn = cconj(buf[p * LS + lpad(L - 1 - m)]);
@@ -276,8 +279,8 @@ __global__ __launch_bounds__(NT) void x_inverse_kernel(const XBatch b,
 // transformed.  The arithmetic is that of x_inverse_kernel, so both give the
 // same bits.  Registers are held to 128 so that four blocks share a compute
 // unit, as many as the LDS of 8 rows of 1024 allows.
-template <int L, int TY>
-__global__ __launch_bounds__(NT, 4) void x_inverse_reg_kernel(const XBatch b,
+template <int L, int TY, int NTX = NT>
+__global__ __launch_bounds__(NTX, 4) void x_inverse_reg_kernel(const XBatch b,
                                                            const float2* __restrict__ tw_all) {
     constexpr int X1 = L + 1;
     constexpr int NP = TY / 2;
@@ -285,8 +288,8 @@ __global__ __launch_bounds__(NT, 4) void x_inverse_reg_kernel(const XBatch b,
     __shared__ float2 buf[NP * LS];
     __shared__ float2 twt[x_tw2<L, 0>() ? tw2_entries(L) : L];
     __shared__ float2 tw2t[x_tw2<L, 0>() ? tw2_entries(2 * L) : L];
-    const auto twL = x_twiddles<L, 0>(twt, tw_all + tw_offset(L));
-    const auto tw2L = x_twiddles_2l<L, 0, false>(tw2t, tw_all + tw_offset(2 * L));
+    const auto twL = x_twiddles<L, 0, NTX>(twt, tw_all + tw_offset(L));
+    const auto tw2L = x_twiddles_2l<L, 0, false, NTX>(tw2t, tw_all + tw_offset(2 * L));
     const int tid = threadIdx.x;
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
@@ -301,7 +304,7 @@ __global__ __launch_bounds__(NT, 4) void x_inverse_reg_kernel(const XBatch b,
     float* dst = H + ((size_t)(c * nz + z) * ny + y0) * L;
     using Rows = RowLines<LS>;
 
-    for (int it = tid; it < (L / 2 + 1) * NP; it += NT) {
+    for (int it = tid; it < (L / 2 + 1) * NP; it += NTX) {
         int p = it % NP, m = it / NP, kx = 2 * m;
         float2 Xa, Xb;
         load_pair(src + (size_t)kx * ny + 2 * p, Xa, Xb, rows - 2 * p);
@@ -314,28 +317,28 @@ __global__ __launch_bounds__(NT, 4) void x_inverse_reg_kernel(const XBatch b,
     }
     // odd inputs kx = 2m + 1, in flight during the even part's transform
     constexpr int NO = (L / 2) * NP;
-    constexpr int PO = (NO + NT - 1) / NT;
+    constexpr int PO = (NO + NTX - 1) / NTX;
     float2 oa[PO], ob[PO];
 #pragma unroll
     for (int q = 0; q < PO; ++q) {
-        const int it = tid + q * NT;
-        if (NO % NT == 0 || it < NO) {
+        const int it = tid + q * NTX;
+        if (NO % NTX == 0 || it < NO) {
             const int p = it % NP, m = it / NP;
             load_pair(src + (size_t)(2 * m + 1) * ny + 2 * p, oa[q], ob[q], rows - 2 * p);
         }
     }
     __syncthreads();
     auto from_lds = [&](int p, int t) { return buf[p * LS + lpad(t)]; };
-    constexpr int RL = tail_radix<L>(), PER = tail_per<L, NP, NT>(), NB = L / RL;
+    constexpr int RL = tail_radix<L>(), PER = tail_per<L, NP, NTX>(), NB = L / RL;
     float2 ie[PER][RL];
-    fft_head<L, +1, NP, NT, Rows, false, true>(buf, twL, from_lds);
-    fft_tail<L, +1, NP, NT, Rows>(buf, twL, ie);
+    fft_head<L, +1, NP, NTX, Rows, false, true>(buf, twL, from_lds);
+    fft_tail<L, +1, NP, NTX, Rows>(buf, twL, ie);
     __syncthreads();
     // Z[2m+1] at slot m, and Z[2L-2m-1] = conj -> slot L-1-m
 #pragma unroll
     for (int q = 0; q < PO; ++q) {
-        const int it = tid + q * NT;
-        if (NO % NT == 0 || it < NO) {
+        const int it = tid + q * NTX;
+        if (NO % NTX == 0 || it < NO) {
             const int p = it % NP, m = it / NP;
             const float2 Xa = oa[q], Xb = ob[q];
             buf[p * LS + lpad(m)] = make_float2(Xa.x - Xb.y, Xa.y + Xb.x);
@@ -344,13 +347,13 @@ __global__ __launch_bounds__(NT, 4) void x_inverse_reg_kernel(const XBatch b,
     }
     __syncthreads();
     float2 io[PER][RL];
-    fft_head<L, +1, NP, NT, Rows, false, true>(buf, twL, from_lds);
-    fft_tail<L, +1, NP, NT, Rows>(buf, twL, io);
+    fft_head<L, +1, NP, NTX, Rows, false, true>(buf, twL, from_lds);
+    fft_tail<L, +1, NP, NTX, Rows>(buf, twL, io);
     // z[t] = IE[t] + W_2L^-t IO[t]; both rows of the pair go straight to H
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const int bb = tid + q * NT;
-        if ((NB * NP) % NT == 0 || bb < NB * NP) {
+        const int bb = tid + q * NTX;
+        if ((NB * NP) % NTX == 0 || bb < NB * NP) {
             int p, j;
             Rows::template split<NB>(bb, p, j);
 #pragma unroll
@@ -440,6 +443,17 @@ int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hi
             b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;       \
         if constexpr (npasses(L) >= 2) {                                                      \
             if (mf == 0) {                                                                    \
+                /* variant 0: the largest row tile on 512 threads, where its first pass */  \
+                /* has a butterfly for each */                                                \
+                constexpr int TYW = XTile<L, 2, false>::TY;                                   \
+                constexpr int NTW = (TYW / 2) * (L / head_radix<L>()) >= 2 * NT ? 2 * NT : NT; \
+                if (V == 0 && NTW > NT) {                                                     \
+                    for (int r = 0; r < b.count; ++r)                                         \
+                        b.start[r + 1] = b.start[r] + ((b.d[r].ny + TYW - 1) / TYW) * b.d[r].nz * 3; \
+                    hipLaunchKernelGGL((x_forward_reg_kernel<L, TYW, NTW>),                   \
+                                       dim3((unsigned)finish_batch(b)), dim3(NTW), 0, s, b, tw); \
+                    break;                                                                    \
+                }                                                                             \
                 hipLaunchKernelGGL((x_forward_reg_kernel<L, TY>),                             \
                                    dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);   \
                 break;                                                                        \
