@@ -30,6 +30,19 @@ __device__ __forceinline__ auto x_twiddles_2l(float2* twt, const float2* __restr
     }
 }
 
+// LDS stride of the NP packed lines of an x block (in float2): the Hermitian
+// separation and the inverse's gather walk element m of all NP lines with
+// consecutive threads on consecutive lines, so 16 neighbouring threads touch
+// elements (p, m) .. (p + NP - 1, m + 16/NP - 1).  A stride of 16/NP modulo 16
+// puts those 16 float2 (128 bytes) on distinct banks; an odd stride made
+// (p + 1, m) and (p, m + 1) collide.
+template <int L, int NP>
+constexpr int x_line_stride() {
+    constexpr int base = lpad_c(L) + 1;
+    constexpr int want = NP >= 16 ? 1 : 16 / NP;
+    return base + ((want - base % 16) + 16) % 16;
+}
+
 // ============================================================================ x
 // One block: component c, plane z, rows y0 .. y0+TY-1 (TY/2 packed pairs).
 // Forward: each pair z = a + i b is transformed twice (even outputs: DFT of z,
@@ -43,7 +56,7 @@ __global__ __launch_bounds__(NT) void x_forward_kernel(const XBatch b,
                                                        const float2* __restrict__ tw_all) {
     constexpr int X1 = PX ? L / 2 + 1 : L + 1;
     constexpr int NP = TY / 2;
-    constexpr int LS = lpad_c(L) + 1;  // odd stride: the pairs of one frequency hit distinct banks
+    constexpr int LS = x_line_stride<L, NP>();
     __shared__ float2 buf[NP * LS];
     __shared__ float2 twt[x_tw2<L, MF>() ? tw2_entries(L) : L];
     const auto twL = x_twiddles<L, MF>(twt, tw_all + tw_offset(L));
@@ -111,7 +124,7 @@ __global__ __launch_bounds__(NTX) void x_forward_reg_kernel(const XBatch b,
                                                            const float2* __restrict__ tw_all) {
     constexpr int X1 = L + 1;
     constexpr int NP = TY / 2;
-    constexpr int LS = lpad_c(L) + 1;
+    constexpr int LS = x_line_stride<L, NP>();
     __shared__ float2 buf[NP * LS];
     __shared__ float2 twt[x_tw2<L, 0>() ? tw2_entries(L) : L];
     const auto twL = x_twiddles<L, 0, NTX>(twt, tw_all + tw_offset(L));
@@ -206,7 +219,7 @@ __global__ __launch_bounds__(NT) void x_inverse_kernel(const XBatch b,
                                                        const float2* __restrict__ tw_all) {
     constexpr int X1 = PX ? L / 2 + 1 : L + 1;
     constexpr int NP = TY / 2;
-    constexpr int LS = lpad_c(L) + 1;  // odd stride: the pairs of one frequency hit distinct banks
+    constexpr int LS = x_line_stride<L, NP>();
     __shared__ float2 buf[NP * LS];
     __shared__ float2 ie[PX ? 1 : NP * LS];
     __shared__ float2 twt[x_tw2<L, MF>() ? tw2_entries(L) : L];
@@ -284,7 +297,7 @@ __global__ __launch_bounds__(NTX, 4) void x_inverse_reg_kernel(const XBatch b,
                                                            const float2* __restrict__ tw_all) {
     constexpr int X1 = L + 1;
     constexpr int NP = TY / 2;
-    constexpr int LS = lpad_c(L) + 1;
+    constexpr int LS = x_line_stride<L, NP>();
     __shared__ float2 buf[NP * LS];
     __shared__ float2 twt[x_tw2<L, 0>() ? tw2_entries(L) : L];
     __shared__ float2 tw2t[x_tw2<L, 0>() ? tw2_entries(2 * L) : L];
