@@ -364,6 +364,18 @@ __global__ __launch_bounds__(CB * 8, 4) void z_convolve_sq_kernel(const ZBatch b
     for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
         for (int r = 0; r < RIN; ++r) v[cc][r] = s2(cc, r);
+    // With 64 columns per block the tensor loads go out with the spectrum loads,
+    // so they are in flight during the forward transforms (48 more registers,
+    // within the 128 that two blocks per compute unit allow); with 32 they are
+    // issued at the product, where they fit without spilling.
+    constexpr bool KEARLY = CB == 64;
+    float kv[6][R];
+    if constexpr (KEARLY) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < 6; ++q) kv[q][r] = kval(q, r);
+    }
     // the last passes' twiddles W^(j 2^d), W = exp(-2 pi i / N_z), as table entries
     const float2* twz = tw_all + tw_offset(NZ);
     TwRun twf;
@@ -392,11 +404,12 @@ __global__ __launch_bounds__(CB * 8, 4) void z_convolve_sq_kernel(const ZBatch b
     for (int r = 0; r < R; ++r) {
         const int kz = j + R * r;
         const float sz = 2 * kz > NZ ? -1.f : 1.f;
-        float kv[6];
+        if constexpr (!KEARLY) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) kv[q] = kval(q, r);
-        const float kxx = kv[0], kyy = kv[1], kzz = kv[2];
-        const float kxy = sy * kv[3], kxz = sz * kv[4], kyz = sy * sz * kv[5];
+            for (int q = 0; q < 6; ++q) kv[q][r] = kval(q, r);
+        }
+        const float kxx = kv[0][r], kyy = kv[1][r], kzz = kv[2][r];
+        const float kxy = sy * kv[3][r], kxz = sz * kv[4][r], kyz = sy * sz * kv[5][r];
         const float2 mx = v[0][r], my = v[1][r], mz = v[2][r];
         auto dot3 = [](float a, float x, float bb, float y, float cc2, float z) {
             return fmaf(cc2, z, fmaf(bb, y, a * x));
