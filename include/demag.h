@@ -313,8 +313,10 @@ int demag_timing_read(demag_plan* plan, double* total_ms, int32_t* launches);
  * loads in flight while the first is transformed.  Variants 1 and 2 give the
  * same bits; variant 0 rounds differently.  Each is deterministic and within
  * the 2e-5 contract.
- * demag_autotune times every variant of every stage on the plan's own buffers
- * (HIP events, 5 launches each; synchronises `stream`), keeps the fastest and
+ * demag_autotune times every variant of every stage inside whole evaluations on
+ * the plan's own buffers (HIP events around the stage's launches, two rounds of
+ * 3 evaluations; synchronises `stream`; earlier per-stage timing records of the
+ * plan are dropped, its timing capacity kept), keeps the fastest and
  * remembers the choice for later plans of the same mesh size in this process
  * (the serving engine's plans included).  Plans made with a BF16 MFMA flag
  * always run the middle tile shape (variant 1, whatever is set);

@@ -847,63 +847,65 @@ int demag_autotune(demag_plan* plan, void* stream) {
         *ms_out = ms;
         return DEMAG_OK;
     };
-    // 1. tile variants, stage by stage, on the first chunk (the MFMA forms exist
-    //    in one tile shape only).  Thin-mesh plans tune their three kernels:
-    //    row pairs per round of the two xz kernels and the thread count (radix
-    //    order) of the y convolution.
-    rc = run_field_single(plan, M, H, 1.0f, s);
-    // Each variant is timed in two rounds (5 launches each) and keeps its faster
-    // round, so one slow round on a busy device does not decide the choice.
-    for (int st = 0; st < 5 && !rc && plan->xz; st += 2) {
-        const int LNY = 2 * g.ny;
-        const int nv = st == 2 ? (LNY >= 512 ? NVARIANTS : 1) : NVARIANTS;
-        if (nv < 2) continue;
-        double best = 1e30;
-        int best_v = plan->variant[st];
-        for (int vr = 0; vr < 2 * nv && !rc; ++vr) {
-            const int v = vr % nv;
-            auto fn = [&]() -> int {
-                switch (st) {
-                    case 0: return launch_xz_forward(one(xzdesc(plan, M, H, 1.0f)), g.nx, g.nz, v, plan->tw, s);
-                    case 2: return launch_yconv(one(ycdesc(plan)), g.ny, g.Nz, v, plan->tw, s);
-                    default: return launch_xz_inverse(one(xzdesc(plan, M, H, 1.0f)), g.nx, g.nz, v, plan->tw, s);
-                }
-            };
-            double ms = 0.0;
-            rc = time_it(fn, 5, &ms);
-            if (!rc && ms < best) {
-                best = ms;
-                best_v = v;
-            }
-        }
-        plan->variant[st] = best_v;
+    // 1. tile variants, stage by stage, timed inside whole evaluations: the
+    //    stage's launches are bracketed by the plan's timing events while every
+    //    other stage runs as it does in use, so the caches hold what they hold
+    //    in use (a stage launched alone and repeatedly keeps its inputs cached
+    //    and can rank its variants differently).  Thin-mesh plans tune their
+    //    three kernels (row pairs per round of the two xz kernels, the thread
+    //    count of the y convolution); the MFMA forms exist in one tile shape.
+    //    Each variant is timed in two rounds of 3 evaluations and keeps its
+    //    faster round, so one slow round on a busy device does not decide.
+    std::vector<int> stages;
+    if (plan->xz) {
+        stages = {0, 4};
+        if (2 * g.ny >= 512) stages.push_back(2);
+    } else if (plan->mf == 0 && g.pbc == 0) {
+        for (int st = 0; st < 5; ++st)
+            if (!((st == 1 || st == 3) && g.ny == 1)) stages.push_back(st);
     }
-    const int per = (g.X1 + plan->nch - 1) / plan->nch;
-    for (int st = 0; st < 5 && !rc && plan->mf == 0 && !plan->xz && g.pbc == 0; ++st) {
-        if ((st == 1 || st == 3) && g.ny == 1) continue;
+    constexpr int REPS = 3;
+    if (!stages.empty() && (rc = demag_timing_enable(plan, REPS * plan->nch))) {
+        cleanup();
+        return rc;
+    }
+    auto stage_ms = [&](int st, double* out) -> int {
+        int r;
+        const int cap = plan->timing_cap;
+        plan->timing_cap = 0;  // warm-up without events
+        r = run_field_single(plan, M, H, 1.0f, s);
+        plan->timing_cap = cap;
+        for (int k = 0; k < DEMAG_NSTAGES; ++k) plan->timing_n[k] = 0;
+        for (int i = 0; i < REPS && !r; ++i) r = run_field_single(plan, M, H, 1.0f, s);
+        double acc = 0.0;
+        for (int i = 0; i < plan->timing_n[st] && !r; ++i) {
+            float ms = 0.f;
+            if (hipEventSynchronize(plan->ev[st][2 * i + 1]) != hipSuccess ||
+                hipEventElapsedTime(&ms, plan->ev[st][2 * i], plan->ev[st][2 * i + 1]) != hipSuccess)
+                r = fail(DEMAG_EHIP, "autotune timing failed");
+            acc += ms;
+        }
+        for (int k = 0; k < DEMAG_NSTAGES; ++k) plan->timing_n[k] = 0;
+        *out = acc;
+        return r;
+    };
+    for (int st : stages) {
+        if (rc) break;
         double best = 1e30;
         int best_v = plan->variant[st];
         for (int vr = 0; vr < 2 * NVARIANTS && !rc; ++vr) {
-            const int v = vr % NVARIANTS;
-            const int nk = g.ny == 1 ? g.X1 : per;
-            auto fn = [&]() -> int {
-                switch (st) {
-                    case 0: return launch_x_forward(one(xdesc(plan, M, H, 1.0f)), g.nx, v, plan->mf, plan->tw, s);
-                    case 1: return launch_y_forward(one(ydesc(plan, 0, nk)), g.ny, v, plan->mf, plan->tw, s);
-                    case 2: return launch_z_convolve(one(zdesc(plan, 0, nk)), g.Nz, v, plan->mf, plan->tw, s);
-                    case 3: return launch_y_inverse(one(ydesc(plan, 0, nk)), g.ny, v, plan->mf, plan->tw, s);
-                    default: return launch_x_inverse(one(xdesc(plan, M, H, 1.0f)), g.nx, v, plan->mf, plan->tw, s);
-                }
-            };
+            plan->variant[st] = vr % NVARIANTS;
             double ms = 0.0;
-            rc = time_it(fn, 5, &ms);
+            rc = stage_ms(st, &ms);
             if (!rc && ms < best) {
                 best = ms;
-                best_v = v;
+                best_v = vr % NVARIANTS;
             }
         }
         plan->variant[st] = best_v;
     }
+    if (!stages.empty()) free_timing(plan);
+    plan->timing_cap = 0;
     // 2. number of chunks, timing the whole evaluation (each count in two rounds)
     if (!rc && g.ny > 1 && !plan->xz) {
         const int nmin = (g.X1 + plan->xc - 1) / plan->xc;
@@ -923,8 +925,9 @@ int demag_autotune(demag_plan* plan, void* stream) {
         }
         plan->nch = best_n;
     }
-    plan->timing_cap = saved_cap;
     cleanup();
+    // per-stage timing as the caller had it (its earlier records are dropped)
+    if (!rc && saved_cap > 0) rc = demag_timing_enable(plan, saved_cap);
     if (rc) return rc;
     if (g.pbc) return DEMAG_OK;  // periodic plans share no tuning with open ones
     std::lock_guard<std::mutex> lk(g_tune_mu);

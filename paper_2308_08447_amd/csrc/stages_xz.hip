@@ -55,6 +55,20 @@ __device__ __forceinline__ void stage_table_n(float2* dst, const float2* __restr
     for (int i = threadIdx.x; i < n; i += NTHR) dst[i] = src[i];
 }
 
+// The x transforms' twiddle table held in LDS with one padding entry per 16:
+// the middle passes read entries at strides of 8, 16 and 32, which without the
+// padding fold onto a few banks.  Same table values, so the same bits.
+struct TwPad {
+    const float2* p;
+    __device__ __forceinline__ float2 operator[](int t) const { return p[t + (t >> 4)]; }
+};
+constexpr int tw_pad_entries(int n) { return n + n / 16; }
+template <int NTHR>
+__device__ __forceinline__ TwPad stage_tw_pad(float2* dst, const float2* __restrict__ src, int n) {
+    for (int i = threadIdx.x; i < n; i += NTHR) dst[i + (i >> 4)] = src[i];
+    return TwPad{dst};
+}
+
 __device__ __forceinline__ size_t t_index(int c, int kz, int NZ, int G, int ny, int kx, int y) {
     return ((((size_t)c * NZ + kz) * G + kx / TKB) * ny + y) * TKB + kx % TKB;
 }
@@ -154,9 +168,9 @@ __global__ __launch_bounds__(XZShape<L>::NTA) void xz_forward_kernel(const XZBat
     using RR = XZRounds<L, NZS, V>;
     constexpr int NTA = S::NTA, L2 = S::L2, LS = S::LS, NZ = Z::NZ, NPR = RR::NPR;
     __shared__ float2 buf[NPR * LS];
-    __shared__ float2 tw2[L2];
+    __shared__ float2 tw2s[tw_pad_entries(L2)];
     __shared__ float nyq[NZS];
-    stage_table_n<NTA>(tw2, tw_all + tw_offset(L2), L2);
+    const TwPad tw2 = stage_tw_pad<NTA>(tw2s, tw_all + tw_offset(L2), L2);
     const int t = threadIdx.x;
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
@@ -466,9 +480,9 @@ __global__ __launch_bounds__(XZShape<L>::NTA) void xz_inverse_kernel(const XZBat
     using RR = XZRounds<L, NZS, V>;
     constexpr int NTA = S::NTA, L2 = S::L2, LS = S::LS, NZ = Z::NZ, NPR = RR::NPR;
     __shared__ float2 buf[NPR * LS];
-    __shared__ float2 tw2[L2];
+    __shared__ float2 tw2s[tw_pad_entries(L2)];
     __shared__ float nyq[NZS];
-    stage_table_n<NTA>(tw2, tw_all + tw_offset(L2), L2);
+    const TwPad tw2 = stage_tw_pad<NTA>(tw2s, tw_all + tw_offset(L2), L2);
     const int t = threadIdx.x;
     const int gid = xcd_tile(blockIdx.x, gridDim.x);
     const int item = batch_item(b, gid);
