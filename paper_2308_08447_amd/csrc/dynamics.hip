@@ -190,24 +190,40 @@ struct MarchTile {
     float v[3][MTY + 2][MTX + 2];
 };
 
-__device__ __forceinline__ void march_fill(MarchTile& t, const AtomArgs& a, const float* __restrict__ F,
-                                           size_t N, int x0, int y0, int z, float3 own, bool inside) {
+// The x/y halo values a thread adds to the tile for plane z: an x halo (left
+// of the first column or right of the last) and a y halo (above the first row
+// or below the last); zero outside the lattice or for threads with no halo.
+struct Halo {
+    float3 hx, hy;
+};
+__device__ __forceinline__ Halo march_halo(const AtomArgs& a, const float* __restrict__ F, size_t N, int x0,
+                                           int y0, int z) {
     const int tx = threadIdx.x % MTX, ty = threadIdx.x / MTX;
     const size_t pl = (size_t)a.nx * a.ny;
+    auto fetch = [&](int gx, int gy) -> float3 {
+        if (gx < 0 || gx >= a.nx || gy < 0 || gy >= a.ny || z >= a.nz) return make_float3(0.f, 0.f, 0.f);
+        return load3(F, (size_t)z * pl + (size_t)gy * a.nx + gx, N);
+    };
+    Halo h{make_float3(0.f, 0.f, 0.f), make_float3(0.f, 0.f, 0.f)};
+    if (tx == 0) h.hx = fetch(x0 - 1, y0 + ty);
+    if (tx == MTX - 1) h.hx = fetch(x0 + MTX, y0 + ty);
+    if (ty == 0) h.hy = fetch(x0 + tx, y0 - 1);
+    if (ty == MTY - 1) h.hy = fetch(x0 + tx, y0 + MTY);
+    return h;
+}
+
+__device__ __forceinline__ void march_fill(MarchTile& t, float3 own, bool inside, const Halo& h) {
+    const int tx = threadIdx.x % MTX, ty = threadIdx.x / MTX;
     auto put = [&](int lx, int ly, float3 val) {
         t.v[0][ly][lx] = val.x;
         t.v[1][ly][lx] = val.y;
         t.v[2][ly][lx] = val.z;
     };
-    auto fetch = [&](int gx, int gy) -> float3 {
-        if (gx < 0 || gx >= a.nx || gy < 0 || gy >= a.ny) return make_float3(0.f, 0.f, 0.f);
-        return load3(F, (size_t)z * pl + (size_t)gy * a.nx + gx, N);
-    };
     put(tx + 1, ty + 1, inside ? own : make_float3(0.f, 0.f, 0.f));
-    if (tx == 0) put(0, ty + 1, fetch(x0 - 1, y0 + ty));
-    if (tx == MTX - 1) put(MTX + 1, ty + 1, fetch(x0 + MTX, y0 + ty));
-    if (ty == 0) put(tx + 1, 0, fetch(x0 + tx, y0 - 1));
-    if (ty == MTY - 1) put(tx + 1, MTY + 1, fetch(x0 + tx, y0 + MTY));
+    if (tx == 0) put(0, ty + 1, h.hx);
+    if (tx == MTX - 1) put(MTX + 1, ty + 1, h.hx);
+    if (ty == 0) put(tx + 1, 0, h.hy);
+    if (ty == MTY - 1) put(tx + 1, MTY + 1, h.hy);
 }
 
 // exchange sum of the tile cell (tx, ty) with open boundaries, then z neighbours
@@ -249,6 +265,9 @@ __device__ __forceinline__ float3 march_field(const AtomArgs& a, const float* __
 
 // STAGE 0: predictor (F = S): f0 = f(S), Sp = S + dt f0.
 // STAGE 1: corrector (F = Sp): S = normalise(S + dt/2 (f0 + f(Sp))).
+// Every global load a plane needs (its z + 1 neighbours, its tile halo and, for
+// the corrector, f0 and S) is issued one plane ahead, so a block's loads are in
+// flight while it computes the plane before instead of after each barrier.
 template <int STAGE>
 __global__ __launch_bounds__(MTX * MTY) void heun_march_kernel(AtomArgs a, const float* __restrict__ F,
                                                              const float* __restrict__ Hdm,
@@ -264,12 +283,32 @@ __global__ __launch_bounds__(MTX * MTY) void heun_march_kernel(AtomArgs a, const
     const bool inside = x < a.nx && y < a.ny;
     const size_t col = (size_t)y * a.nx + x;
     const int zend = min(z0 + MZC, a.nz);
-    float3 zero = make_float3(0.f, 0.f, 0.f);
-    float3 below = (inside && z0 > 0) ? load3(F, (size_t)(z0 - 1) * pl + col, N) : zero;
-    float3 cur = inside ? load3(F, (size_t)z0 * pl + col, N) : zero;
+    const float3 zero = make_float3(0.f, 0.f, 0.f);
+    auto column = [&](const float* src, int z) {   // this thread's value of plane z, zero outside
+        return (inside && z >= 0 && z < a.nz) ? load3(src, (size_t)z * pl + col, N) : zero;
+    };
+    float3 below = column(F, z0 - 1);
+    float3 cur = column(F, z0);
+    float3 above = column(F, z0 + 1);
+    Halo halo = march_halo(a, F, N, x0, y0, z0);
+    float3 g = zero, sv = zero;   // corrector: f0 and S of the current plane
+    if constexpr (STAGE == 1) {
+        g = column(f0, z0);
+        sv = column(Sp_or_S, z0);
+    }
     for (int z = z0; z < zend; ++z) {
-        float3 above = (inside && z + 1 < a.nz) ? load3(F, (size_t)(z + 1) * pl + col, N) : zero;
-        march_fill(tile, a, F, N, x0, y0, z, cur, inside);
+        // next plane's loads (consumed in the next iteration)
+        const bool more = z + 1 < zend;
+        const float3 above2 = more ? column(F, z + 2) : zero;
+        const Halo halo2 = more ? march_halo(a, F, N, x0, y0, z + 1) : halo;
+        float3 g2 = zero, sv2 = zero;
+        if constexpr (STAGE == 1) {
+            if (more) {
+                g2 = column(f0, z + 1);
+                sv2 = column(Sp_or_S, z + 1);
+            }
+        }
+        march_fill(tile, cur, inside, halo);
         __syncthreads();
         if (inside) {
             const size_t i = (size_t)z * pl + col;
@@ -279,10 +318,8 @@ __global__ __launch_bounds__(MTX * MTY) void heun_march_kernel(AtomArgs a, const
                 store3(f0, i, N, f);
                 store3(Sp_or_S, i, N, make_float3(cur.x + a.dt * f.x, cur.y + a.dt * f.y, cur.z + a.dt * f.z));
             } else {
-                float3 g = load3(f0, i, N);
-                float3 s = load3(Sp_or_S, i, N);
                 float h = 0.5f * a.dt;
-                float3 v = make_float3(s.x + h * (g.x + f.x), s.y + h * (g.y + f.y), s.z + h * (g.z + f.z));
+                float3 v = make_float3(sv.x + h * (g.x + f.x), sv.y + h * (g.y + f.y), sv.z + h * (g.z + f.z));
                 float inv = rsqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
                 store3(Sp_or_S, i, N, make_float3(v.x * inv, v.y * inv, v.z * inv));
             }
@@ -290,6 +327,10 @@ __global__ __launch_bounds__(MTX * MTY) void heun_march_kernel(AtomArgs a, const
         __syncthreads();
         below = cur;
         cur = above;
+        above = above2;
+        halo = halo2;
+        g = g2;
+        sv = sv2;
     }
 }
 
