@@ -469,8 +469,10 @@ def switching_bench(pkg, args):
 
 def thin_film_block(pkg, args):
     """The thin-film LLG workload, 512 x 512 x 16 cells of 4 nm, RK4 dt = 1e-13 s:
-    timed RK4 steps (four H_d evaluations and four fused exchange + LLG stage
-    updates each) with per-stage event timing, the same steps with the
+    RK4 steps (four H_d evaluations and four fused exchange + LLG stage updates
+    each), timed once with per-stage events (the stage table) and once as one
+    llg_step call without events (the step time: an event between every two
+    kernels adds about 0.15 ms per step at this size), the same steps with the
     extrapolated H_d, the film periodic in x and y, and demag_field alone."""
     import torch
     import workloads as W
@@ -505,11 +507,22 @@ def thin_film_block(pkg, args):
     for _ in range(args.steps):
         pkg.llg_step(plan, m, params, cfg["dt"], 1, stream)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    elapsed_ev = time.perf_counter() - t0
     stages = pkg.demag_timing_read(plan)
     pkg.demag_timing_enable(plan, 0)
 
     m_plain = m.clone()
+    # the step time itself: the same number of steps in one llg_step call (the
+    # captured step replayed), with no stage events between the kernels, on a
+    # copy of m (the graph is captured by the first call on that tensor)
+    mc = m.clone()
+    pkg.llg_step(plan, mc, params, cfg["dt"], 2, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pkg.llg_step(plan, mc, params, cfg["dt"], args.steps, stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    del mc
 
     # the same steps with one H_d per RK4 step (quartic extrapolation of H_d at
     # the sub-steps once five step-start fields exist): wall time and the
@@ -544,13 +557,17 @@ def thin_film_block(pkg, args):
         pkg.llg_step(plan_p, mp, params, cfg["dt"], 1, stream)
     torch.cuda.synchronize()
     pkg.demag_timing_enable(plan_p, 4 * args.steps * pkg.demag_get_chunks(plan_p))
-    tp0 = time.perf_counter()
     for _ in range(args.steps):
         pkg.llg_step(plan_p, mp, params, cfg["dt"], 1, stream)
     torch.cuda.synchronize()
-    elapsed_p = time.perf_counter() - tp0
     stages_p = pkg.demag_timing_read(plan_p)
     pkg.demag_timing_enable(plan_p, 0)
+    pkg.llg_step(plan_p, mp, params, cfg["dt"], 2, stream)   # captures the step
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    pkg.llg_step(plan_p, mp, params, cfg["dt"], args.steps, stream)
+    torch.cuda.synchronize()
+    elapsed_p = time.perf_counter() - tp0
     pkg.demag_destroy(plan_p)
     per_stage_p = _stage_table(stage_bytes(n, 5, pbc), stages_p, 4 * args.steps)
     hd_p = sum(v["us_per_eval"] for k, v in per_stage_p.items() if k != "llg")
@@ -625,6 +642,7 @@ def thin_film_block(pkg, args):
                                                 per_stage[dom]["launches"] / evals),
                      "bytes_per_launch": per_stage[dom]["bytes_per_launch"]},
         "stages": per_stage,
+        "ms_per_step_with_stage_events": round(1e3 * elapsed_ev / args.steps, 4),
         "demag_field_gcells_per_s": round(cells / t_field / 1e9, 3),
         "demag_field_us": round(1e6 * t_field, 1),
         "demag_field_effective_frac": round(b5 / t_field / 1e9 / HBM_PEAK_GBS, 4),
