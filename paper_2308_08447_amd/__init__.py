@@ -5,8 +5,13 @@ Every function here only marshals arguments to the shared library
 computation runs in the library's HIP kernels.  There is no fallback: if the
 library is missing or cannot be loaded, ``load()`` raises.
 
-Device arrays are passed as raw pointers; with PyTorch use ``t.data_ptr()`` and
-``torch.cuda.current_stream().cuda_stream`` for the stream.
+Device arrays are passed as torch GPU tensors or as raw device addresses (ints);
+streams as torch streams or raw handles.  A torch tensor is checked before the
+call (on the GPU, float32, contiguous, at least 3 n_x n_y n_z floats for the
+plan's mesh), as are the host arrays of the server (float32, C-contiguous, the
+request's size): the ABI takes plain pointers and cannot tell a host or short
+buffer from a field, so a bad one raises ValueError here instead of faulting
+the GPU.  Raw addresses are passed through unchecked.
 """
 
 import ctypes
@@ -170,6 +175,50 @@ def _ptr(x):
     return x.data_ptr()
 
 
+# Cell count of each live plan (demag and atomistic) and of each pending served
+# request, so that tensor arguments can be checked before they reach a kernel:
+# the C ABI takes plain pointers and cannot tell a host buffer, a float64 tensor
+# or a short one from a valid field.
+_PLAN_CELLS = {}
+_REQ_CELLS = {}
+
+
+def _cells(mesh):
+    return int(mesh.nx) * int(mesh.ny) * int(mesh.nz)
+
+
+def _dev(x, need, name):
+    """Pointer of a device float32 buffer of at least `need` elements.  Torch
+    tensors are checked (GPU, float32, contiguous, size); an int is taken as a
+    raw device address, unchecked, as the C ABI takes it."""
+    if x is None or isinstance(x, int):
+        return x
+    if not getattr(x, "is_cuda", False):
+        raise ValueError(f"{name} must be a GPU tensor: the kernels cannot read host memory")
+    if str(x.dtype) != "torch.float32":
+        raise ValueError(f"{name} must be float32, not {x.dtype}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous ([3][nz][ny][nx], x fastest)")
+    if need is not None and x.numel() < need:
+        raise ValueError(f"{name} holds {x.numel()} floats; the plan needs {need}")
+    return x.data_ptr()
+
+
+def _field(plan, x, name):
+    cells = _PLAN_CELLS.get(plan)
+    return _dev(x, None if cells is None else 3 * cells, name)
+
+
+def _host(a, need, name):
+    """Host float32 C-contiguous numpy array of exactly `need` elements."""
+    import numpy as np
+    if not isinstance(a, np.ndarray) or a.dtype != np.float32 or not a.flags["C_CONTIGUOUS"]:
+        raise ValueError(f"{name} must be a C-contiguous float32 numpy array")
+    if need is not None and a.size != need:
+        raise ValueError(f"{name} holds {a.size} floats; the mesh has {need}")
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
 def _stream(stream):
     if stream is None:
         return None
@@ -185,11 +234,13 @@ def demag_setup(mesh, flags=DEMAG_FP32, stream=None):
         mesh = demag_mesh(*mesh)
     out = ctypes.c_void_p()
     _check(load().demag_setup(ctypes.byref(mesh), flags, _stream(stream), ctypes.byref(out)))
+    _PLAN_CELLS[out.value] = _cells(mesh)
     return out.value
 
 
 def demag_field(plan, M, H, stream=None):
-    return _check(load().demag_field(plan, _ptr(M), _ptr(H), _stream(stream)))
+    pm, ph = _field(plan, M, "M"), _field(plan, H, "H")
+    return _check(load().demag_field(plan, pm, ph, _stream(stream)))
 
 
 def demag_plan_bytes(mesh, flags=DEMAG_FP32):
@@ -199,10 +250,12 @@ def demag_plan_bytes(mesh, flags=DEMAG_FP32):
 
 
 def demag_get_kernel(plan, dst, count, stream=None):
-    return _check(load().demag_get_kernel(plan, _ptr(dst), count, _stream(stream)))
+    pd = _dev(dst, int(count), "dst")
+    return _check(load().demag_get_kernel(plan, pd, count, _stream(stream)))
 
 
 def demag_destroy(plan):
+    _PLAN_CELLS.pop(plan, None)
     return _check(load().demag_destroy(plan))
 
 
@@ -211,7 +264,8 @@ def llg_step(plan, m, params, dt, nsteps, stream=None):
     if not isinstance(params, llg_params):
         Ms, A, alpha, gamma, hz = params
         params = llg_params(Ms, A, alpha, gamma, (ctypes.c_double * 3)(*hz))
-    return _check(load().llg_step(plan, _ptr(m), ctypes.byref(params), dt, nsteps, _stream(stream)))
+    pm = _field(plan, m, "m")
+    return _check(load().llg_step(plan, pm, ctypes.byref(params), dt, nsteps, _stream(stream)))
 
 
 def llg_step_noalloc(plan, m, params, dt, nsteps, stream=None):
@@ -220,7 +274,8 @@ def llg_step_noalloc(plan, m, params, dt, nsteps, stream=None):
     if not isinstance(params, llg_params):
         Ms, A, alpha, gamma, hz = params
         params = llg_params(Ms, A, alpha, gamma, (ctypes.c_double * 3)(*hz))
-    return _check(load().llg_step_noalloc(plan, _ptr(m), ctypes.byref(params), dt, nsteps,
+    pm = _field(plan, m, "m")
+    return _check(load().llg_step_noalloc(plan, pm, ctypes.byref(params), dt, nsteps,
                                           _stream(stream)))
 
 
@@ -230,7 +285,8 @@ def llg_noalloc_max_cells():
 
 def demag_field_mean(plan, v, out, stream=None):
     """out[0:3] (device) = mean of each component of the [3][N] field v (device)."""
-    return _check(load().demag_field_mean(plan, _ptr(v), _ptr(out), _stream(stream)))
+    pv, po = _field(plan, v, "v"), _dev(out, 3, "out")
+    return _check(load().demag_field_mean(plan, pv, po, _stream(stream)))
 
 
 def llg_reset(plan):
@@ -291,6 +347,7 @@ def atom_setup(mesh, flags=DEMAG_FP32, stream=None):
         mesh = atom_mesh(*mesh)
     out = ctypes.c_void_p()
     _check(load().atom_setup(ctypes.byref(mesh), flags, _stream(stream), ctypes.byref(out)))
+    _PLAN_CELLS[out.value] = _cells(mesh)
     return out.value
 
 
@@ -299,10 +356,12 @@ def atom_step(plan, S, params, dt, nsteps, stream=None):
     if not isinstance(params, atom_params):
         J, mu_s, alpha, gamma, hz = params
         params = atom_params(J, mu_s, alpha, gamma, (ctypes.c_double * 3)(*hz))
-    return _check(load().atom_step(plan, _ptr(S), ctypes.byref(params), dt, nsteps, _stream(stream)))
+    ps = _field(plan, S, "S")
+    return _check(load().atom_step(plan, ps, ctypes.byref(params), dt, nsteps, _stream(stream)))
 
 
 def atom_destroy(plan):
+    _PLAN_CELLS.pop(plan, None)
     return _check(load().atom_destroy(plan))
 
 
@@ -325,17 +384,21 @@ def serve_submit(server, mesh, params, dt, nsteps, m0_host):
     if not isinstance(mesh, demag_mesh):
         mesh = demag_mesh(*mesh)
     m0 = np.ascontiguousarray(m0_host, dtype=np.float32)
+    pm = _host(m0, 3 * _cells(mesh), "m0_host")
     rid = ctypes.c_uint64()
     _check(load().serve_submit(server, ctypes.byref(mesh), ctypes.byref(_llg(params)), dt, nsteps,
-                               m0.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rid)))
+                               pm, ctypes.byref(rid)))
+    _REQ_CELLS[(server, rid.value)] = _cells(mesh)
     return rid.value
 
 
 def serve_wait(server, request_id, m_out_host):
     """Blocks until done; fills m_out_host (float32, C-contiguous); returns latency in s."""
+    cells = _REQ_CELLS.get((server, request_id))
+    pm = _host(m_out_host, None if cells is None else 3 * cells, "m_out_host")
     lat = ctypes.c_double()
-    _check(load().serve_wait(server, request_id, m_out_host.ctypes.data_as(ctypes.c_void_p),
-                             ctypes.byref(lat)))
+    _check(load().serve_wait(server, request_id, pm, ctypes.byref(lat)))
+    _REQ_CELLS.pop((server, request_id), None)
     return lat.value
 
 
@@ -346,6 +409,8 @@ def serve_get_stats(server):
 
 
 def serve_close(server):
+    for key in [k for k in _REQ_CELLS if k[0] == server]:
+        del _REQ_CELLS[key]
     return _check(load().serve_close(server))
 
 

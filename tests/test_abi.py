@@ -168,3 +168,68 @@ def test_inplace_flag_on_host():
     for f in (0, pkg.DEMAG_BF16X3_MFMA, pkg.DEMAG_EXTRAPOLATE_HD, pkg.pbc_flags(x=True, images=2)):
         assert pkg.demag_plan_bytes(mesh, flags=f | pkg.DEMAG_INPLACE) == pkg.demag_plan_bytes(mesh, flags=f) > 0
     assert pkg.demag_plan_bytes(mesh, flags=1 << 30) == 0
+
+
+class _DeviceStandIn:
+    """Has the attributes the binding checks on a torch GPU tensor (no GPU here)."""
+
+    def __init__(self, n, dtype="torch.float32", contiguous=True, cuda=True):
+        self.n, self.dtype, self.contiguous, self.is_cuda = n, dtype, contiguous, cuda
+
+    def is_contiguous(self):
+        return self.contiguous
+
+    def numel(self):
+        return self.n
+
+    def data_ptr(self):
+        return 0x1000                   # every check runs before the library is called
+
+
+def test_binding_refuses_bad_tensors_before_the_library():
+    """The C ABI takes plain pointers, so the binding checks torch arguments
+    against the plan's mesh first: a host tensor, another dtype, a strided view
+    or a short buffer raises ValueError and nothing is called."""
+    torch = pytest.importorskip("torch")
+    plan = 0x5EED0                      # a handle the binding knows, never dereferenced
+    pkg._PLAN_CELLS[plan] = 8 * 4 * 2
+    need = 3 * 8 * 4 * 2
+    try:
+        good = _DeviceStandIn(need)
+        with pytest.raises(ValueError, match="GPU tensor"):
+            pkg.demag_field(plan, torch.zeros(need), good)
+        with pytest.raises(ValueError, match="float32"):
+            pkg.demag_field(plan, _DeviceStandIn(need, dtype="torch.float64"), good)
+        with pytest.raises(ValueError, match="contiguous"):
+            pkg.llg_step(plan, _DeviceStandIn(need, contiguous=False), (8e5, 1.3e-11, 0.1, 2.2e5, (0, 0, 0)),
+                         1e-13, 1)
+        with pytest.raises(ValueError, match="needs 192"):
+            pkg.llg_step_noalloc(plan, _DeviceStandIn(need - 1), (8e5, 1.3e-11, 0.1, 2.2e5, (0, 0, 0)),
+                                 1e-13, 1)
+        with pytest.raises(ValueError, match="needs 192"):
+            pkg.atom_step(plan, _DeviceStandIn(10), (1e-21, 2.0, 0.1, 1.76e11, (0, 0, 0)), 1e-15, 1)
+        with pytest.raises(ValueError, match="needs 3"):
+            pkg.demag_field_mean(plan, good, _DeviceStandIn(2))
+        with pytest.raises(ValueError, match="needs 100"):
+            pkg.demag_get_kernel(plan, _DeviceStandIn(99), 100)
+    finally:
+        del pkg._PLAN_CELLS[plan]
+
+
+def test_binding_refuses_bad_host_arrays_before_the_library():
+    import numpy as np
+    server = 0x5EED1
+    mesh = (8, 4, 2, 4e-9, 4e-9, 4e-9)
+    params = (8e5, 1.3e-11, 0.1, 2.2e5, (0, 0, 0))
+    with pytest.raises(ValueError, match="the mesh has 192"):
+        pkg.serve_submit(server, mesh, params, 1e-13, 1, np.zeros(191, np.float32))
+    pkg._REQ_CELLS[(server, 7)] = 8 * 4 * 2
+    try:
+        with pytest.raises(ValueError, match="float32"):
+            pkg.serve_wait(server, 7, np.zeros(192, np.float64))
+        with pytest.raises(ValueError, match="the mesh has 192"):
+            pkg.serve_wait(server, 7, np.zeros(100, np.float32))
+        with pytest.raises(ValueError, match="C-contiguous"):
+            pkg.serve_wait(server, 7, np.zeros((192, 2), np.float32)[:, 0])
+    finally:
+        del pkg._REQ_CELLS[(server, 7)]
