@@ -283,12 +283,12 @@ enum {
  * demag_timing_enable -- when max_records > 0, every later stage launch of this
  * plan is bracketed by a pair of HIP events on its stream (up to max_records
  * launches per stage; further launches are not timed).  0 disables timing and
- * frees the events.  Timing adds two event records per launch, and each
- * record is a queue packet between two kernels: it does not change a kernel's
- * duration, but it lengthens the gaps between kernels (about 0.15 ms per RK4
- * step, 16 kernels, on 512 x 512 x 16 cells), so time whole steps or
- * evaluations with timing disabled.  llg_step with nsteps >= 2 replays its
- * captured step only while timing is disabled.
+ * frees the events.  Each timed launch takes a record's two events
+ * (hipExtLaunchKernelGGL), so they hold the kernel's own start and end, as a
+ * kernel trace sees them.  They still lengthen the gaps between kernels a
+ * little (about 0.07 ms per RK4 step of 16 kernels on 512 x 512 x 16 cells),
+ * so time whole steps or evaluations with timing disabled.  llg_step with
+ * nsteps >= 2 replays its captured step only while timing is disabled.
  */
 int demag_timing_enable(demag_plan* plan, int32_t max_records);
 

@@ -273,7 +273,12 @@ int ensure_rk(demag_plan* p) {
     return dev_alloc((void**)&p->rk, rk_bytes(p->g), "RK4 buffers");
 }
 
-// Brackets one stage launch with events when timing is enabled on the plan.
+thread_local LaunchEvents g_launch_events;
+
+// Times one stage launch when timing is enabled on the plan: the launcher's
+// kernel takes the record's two events (DM_LAUNCH), so they mark the kernel's
+// own start and end.  A launcher that returns without a kernel leaves them to
+// be recorded here, back to back.
 struct StageTimer {
     demag_plan* p;
     int stage;
@@ -282,11 +287,16 @@ struct StageTimer {
     StageTimer(demag_plan* p_, int stage_, hipStream_t s_) : p(p_), stage(stage_), s(s_) {
         if (p && p->timing_cap > 0 && p->timing_n[stage] < p->timing_cap) {
             slot = p->timing_n[stage]++;
-            (void)hipEventRecord(p->ev[stage][2 * slot], s);
+            g_launch_events = LaunchEvents{p->ev[stage][2 * slot], p->ev[stage][2 * slot + 1]};
         }
     }
     ~StageTimer() {
-        if (slot >= 0) (void)hipEventRecord(p->ev[stage][2 * slot + 1], s);
+        if (slot < 0) return;
+        if (g_launch_events.start) {
+            g_launch_events = LaunchEvents{};
+            (void)hipEventRecord(p->ev[stage][2 * slot], s);
+            (void)hipEventRecord(p->ev[stage][2 * slot + 1], s);
+        }
     }
 };
 

@@ -345,8 +345,7 @@ int launch_llg_stage(LLGBatch b, int stage, hipStream_t stream) {
         size_t P = (size_t)b.d[r].nx * b.d[r].ny;
         b.start[r + 1] = b.start[r] + (int)blocks_for(P) * b.d[r].nz;
     }
-    hipLaunchKernelGGL(llg_stage_kernel, dim3((unsigned)b.start[b.count]), dim3(256), 0, stream, b,
-                       stage);
+    DM_LAUNCH(llg_stage_kernel, dim3((unsigned)b.start[b.count]), dim3(256), 0, stream, b, stage);
     DM_CHECK_LAUNCH();
     return DEMAG_OK;
 }

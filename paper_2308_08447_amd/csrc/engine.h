@@ -1,6 +1,7 @@
 // engine.h -- internal declarations shared by the HIP sources of the demag engine.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -22,6 +23,27 @@ int fail(int code, const std::string& msg);
             return ::dm::fail(DEMAG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 #define DM_CHECK_LAUNCH() DM_HIP(hipGetLastError())
+
+// ---- stage timing -----------------------------------------------------------
+// While a plan's stage timer is open on this thread, the next kernel started
+// through DM_LAUNCH takes the timer's start and stop events
+// (hipExtLaunchKernelGGL), so they record the kernel's own start and end
+// rather than queue positions around its dispatch.  Otherwise DM_LAUNCH is a
+// plain launch.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchEvents g_launch_events;
+#define DM_LAUNCH(KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                                     \
+    do {                                                                                       \
+        const ::dm::LaunchEvents ev_ = ::dm::g_launch_events;                                  \
+        ::dm::g_launch_events = ::dm::LaunchEvents{};                                          \
+        if (ev_.start)                                                                         \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, ev_.start, ev_.stop, 0u,  \
+                                  __VA_ARGS__);                                                \
+        else                                                                                   \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);               \
+    } while (0)
 
 // ---- geometry ---------------------------------------------------------------
 // Workgroups are dispatched to the 8 XCDs round-robin.  Renumber them so that

@@ -399,7 +399,7 @@ int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hi
     if (nx == 1) {
         for (int r = 0; r < b.count; ++r) {
             size_t n = (size_t)3 * b.d[r].nz * b.d[r].ny;
-            hipLaunchKernelGGL(x_copy_forward_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+            DM_LAUNCH(x_copy_forward_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                                s, b.d[r].M, b.d[r].S1, n, b.d[r].scale);
         }
         DM_CHECK_LAUNCH();
@@ -415,7 +415,7 @@ int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hi
         b.start[0] = 0;                                                                           \
         for (int r = 0; r < b.count; ++r)                                                         \
             b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;           \
-        hipLaunchKernelGGL((x_forward_kernel<L, TY, 0, true>), dim3((unsigned)finish_batch(b)),       \
+        DM_LAUNCH((x_forward_kernel<L, TY, 0, true>), dim3((unsigned)finish_batch(b)),       \
                            dim3(NT), 0, s, b, tw);                                                \
         break;                                                                                    \
     }
@@ -436,7 +436,7 @@ int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hi
         b.start[0] = 0;                                                                           \
         for (int r = 0; r < b.count; ++r)                                                         \
             b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;           \
-        hipLaunchKernelGGL((x_forward_kernel<L, TY, 0, false>), dim3((unsigned)finish_batch(b)),      \
+        DM_LAUNCH((x_forward_kernel<L, TY, 0, false>), dim3((unsigned)finish_batch(b)),      \
                            dim3(NT), 0, s, b, tw);                                                \
         break;                                                                                    \
     }
@@ -463,16 +463,16 @@ int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hi
                 if (V == 0 && NTW > NT) {                                                     \
                     for (int r = 0; r < b.count; ++r)                                         \
                         b.start[r + 1] = b.start[r] + ((b.d[r].ny + TYW - 1) / TYW) * b.d[r].nz * 3; \
-                    hipLaunchKernelGGL((x_forward_reg_kernel<L, TYW, NTW>),                   \
+                    DM_LAUNCH((x_forward_reg_kernel<L, TYW, NTW>),                   \
                                        dim3((unsigned)finish_batch(b)), dim3(NTW), 0, s, b, tw); \
                     break;                                                                    \
                 }                                                                             \
-                hipLaunchKernelGGL((x_forward_reg_kernel<L, TY>),                             \
+                DM_LAUNCH((x_forward_reg_kernel<L, TY>),                             \
                                    dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);   \
                 break;                                                                        \
             }                                                                                 \
         }                                                                                     \
-        DM_MF_DISPATCH(V, hipLaunchKernelGGL((x_forward_kernel<L, TY, MFv>),                  \
+        DM_MF_DISPATCH(V, DM_LAUNCH((x_forward_kernel<L, TY, MFv>),                  \
                            dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)          \
     }
 #define CASE(Lv)                    \
@@ -496,7 +496,7 @@ int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hi
     if (nx == 1) {
         for (int r = 0; r < b.count; ++r) {
             size_t n = (size_t)3 * b.d[r].nz * b.d[r].ny;
-            hipLaunchKernelGGL(x_copy_inverse_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+            DM_LAUNCH(x_copy_inverse_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                                s, b.d[r].S1, b.d[r].H, n);
         }
         DM_CHECK_LAUNCH();
@@ -512,7 +512,7 @@ int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hi
         b.start[0] = 0;                                                                           \
         for (int r = 0; r < b.count; ++r)                                                         \
             b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;           \
-        hipLaunchKernelGGL((x_inverse_kernel<L, TY, 0, true>), dim3((unsigned)finish_batch(b)),       \
+        DM_LAUNCH((x_inverse_kernel<L, TY, 0, true>), dim3((unsigned)finish_batch(b)),       \
                            dim3(NT), 0, s, b, tw);                                                \
         break;                                                                                    \
     }
@@ -533,7 +533,7 @@ int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hi
         b.start[0] = 0;                                                                           \
         for (int r = 0; r < b.count; ++r)                                                         \
             b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;           \
-        hipLaunchKernelGGL((x_inverse_kernel<L, TY, 0, false>), dim3((unsigned)finish_batch(b)),      \
+        DM_LAUNCH((x_inverse_kernel<L, TY, 0, false>), dim3((unsigned)finish_batch(b)),      \
                            dim3(NT), 0, s, b, tw);                                                \
         break;                                                                                    \
     }
@@ -556,12 +556,12 @@ int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hi
             b.start[r + 1] = b.start[r] + ((b.d[r].ny + ty - 1) / ty) * b.d[r].nz * 3;       \
         if constexpr (V >= 1 && npasses(L) >= 2) {                                            \
             if (reg) {                                                                        \
-                hipLaunchKernelGGL((x_inverse_reg_kernel<L, TYR>),                            \
+                DM_LAUNCH((x_inverse_reg_kernel<L, TYR>),                            \
                                    dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);   \
                 break;                                                                        \
             }                                                                                 \
         }                                                                                     \
-        DM_MF_DISPATCH(V, hipLaunchKernelGGL((x_inverse_kernel<L, TY, MFv>),                  \
+        DM_MF_DISPATCH(V, DM_LAUNCH((x_inverse_kernel<L, TY, MFv>),                  \
                            dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)          \
     }
 #define CASE(Lv)                    \
