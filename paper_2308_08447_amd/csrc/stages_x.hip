@@ -400,7 +400,7 @@ int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hi
         for (int r = 0; r < b.count; ++r) {
             size_t n = (size_t)3 * b.d[r].nz * b.d[r].ny;
             DM_LAUNCH(x_copy_forward_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                               s, b.d[r].M, b.d[r].S1, n, b.d[r].scale);
+                      s, b.d[r].M, b.d[r].S1, n, b.d[r].scale);
         }
         DM_CHECK_LAUNCH();
         return DEMAG_OK;
@@ -415,8 +415,8 @@ int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hi
         b.start[0] = 0;                                                                           \
         for (int r = 0; r < b.count; ++r)                                                         \
             b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;           \
-        DM_LAUNCH((x_forward_kernel<L, TY, 0, true>), dim3((unsigned)finish_batch(b)),       \
-                           dim3(NT), 0, s, b, tw);                                                \
+        DM_LAUNCH((x_forward_kernel<L, TY, 0, true>), dim3((unsigned)finish_batch(b)),           \
+                  dim3(NT), 0, s, b, tw);                                                        \
         break;                                                                                    \
     }
             DM_POW2_CASES(CASE)
@@ -436,8 +436,8 @@ int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hi
         b.start[0] = 0;                                                                           \
         for (int r = 0; r < b.count; ++r)                                                         \
             b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;           \
-        DM_LAUNCH((x_forward_kernel<L, TY, 0, false>), dim3((unsigned)finish_batch(b)),      \
-                           dim3(NT), 0, s, b, tw);                                                \
+        DM_LAUNCH((x_forward_kernel<L, TY, 0, false>), dim3((unsigned)finish_batch(b)),          \
+                  dim3(NT), 0, s, b, tw);                                                        \
         break;                                                                                    \
     }
             DM_MIXED_CASES(CASE)
@@ -463,17 +463,17 @@ int launch_x_forward(XBatch b, int nx, int variant, int mf, const float2* tw, hi
                 if (V == 0 && NTW > NT) {                                                     \
                     for (int r = 0; r < b.count; ++r)                                         \
                         b.start[r + 1] = b.start[r] + ((b.d[r].ny + TYW - 1) / TYW) * b.d[r].nz * 3; \
-                    DM_LAUNCH((x_forward_reg_kernel<L, TYW, NTW>),                   \
-                                       dim3((unsigned)finish_batch(b)), dim3(NTW), 0, s, b, tw); \
+                    DM_LAUNCH((x_forward_reg_kernel<L, TYW, NTW>),                                   \
+                              dim3((unsigned)finish_batch(b)), dim3(NTW), 0, s, b, tw);              \
                     break;                                                                    \
                 }                                                                             \
-                DM_LAUNCH((x_forward_reg_kernel<L, TY>),                             \
-                                   dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);   \
+                DM_LAUNCH((x_forward_reg_kernel<L, TY>),                                      \
+                          dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);            \
                 break;                                                                        \
             }                                                                                 \
         }                                                                                     \
-        DM_MF_DISPATCH(V, DM_LAUNCH((x_forward_kernel<L, TY, MFv>),                  \
-                           dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)          \
+        DM_MF_DISPATCH(V, DM_LAUNCH((x_forward_kernel<L, TY, MFv>),                           \
+                  dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)                   \
     }
 #define CASE(Lv)                    \
     case Lv: {                      \
@@ -497,7 +497,7 @@ int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hi
         for (int r = 0; r < b.count; ++r) {
             size_t n = (size_t)3 * b.d[r].nz * b.d[r].ny;
             DM_LAUNCH(x_copy_inverse_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                               s, b.d[r].S1, b.d[r].H, n);
+                      s, b.d[r].S1, b.d[r].H, n);
         }
         DM_CHECK_LAUNCH();
         return DEMAG_OK;
@@ -512,8 +512,8 @@ int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hi
         b.start[0] = 0;                                                                           \
         for (int r = 0; r < b.count; ++r)                                                         \
             b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;           \
-        DM_LAUNCH((x_inverse_kernel<L, TY, 0, true>), dim3((unsigned)finish_batch(b)),       \
-                           dim3(NT), 0, s, b, tw);                                                \
+        DM_LAUNCH((x_inverse_kernel<L, TY, 0, true>), dim3((unsigned)finish_batch(b)),           \
+                  dim3(NT), 0, s, b, tw);                                                        \
         break;                                                                                    \
     }
             DM_POW2_CASES(CASE)
@@ -533,8 +533,8 @@ int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hi
         b.start[0] = 0;                                                                           \
         for (int r = 0; r < b.count; ++r)                                                         \
             b.start[r + 1] = b.start[r] + ((b.d[r].ny + TY - 1) / TY) * b.d[r].nz * 3;           \
-        DM_LAUNCH((x_inverse_kernel<L, TY, 0, false>), dim3((unsigned)finish_batch(b)),      \
-                           dim3(NT), 0, s, b, tw);                                                \
+        DM_LAUNCH((x_inverse_kernel<L, TY, 0, false>), dim3((unsigned)finish_batch(b)),          \
+                  dim3(NT), 0, s, b, tw);                                                        \
         break;                                                                                    \
     }
             DM_MIXED_CASES(CASE)
@@ -556,13 +556,13 @@ int launch_x_inverse(XBatch b, int nx, int variant, int mf, const float2* tw, hi
             b.start[r + 1] = b.start[r] + ((b.d[r].ny + ty - 1) / ty) * b.d[r].nz * 3;       \
         if constexpr (V >= 1 && npasses(L) >= 2) {                                            \
             if (reg) {                                                                        \
-                DM_LAUNCH((x_inverse_reg_kernel<L, TYR>),                            \
-                                   dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);   \
+                DM_LAUNCH((x_inverse_reg_kernel<L, TYR>),                                     \
+                          dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);            \
                 break;                                                                        \
             }                                                                                 \
         }                                                                                     \
-        DM_MF_DISPATCH(V, DM_LAUNCH((x_inverse_kernel<L, TY, MFv>),                  \
-                           dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)          \
+        DM_MF_DISPATCH(V, DM_LAUNCH((x_inverse_kernel<L, TY, MFv>),                           \
+                  dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)                   \
     }
 #define CASE(Lv)                    \
     case Lv: {                      \

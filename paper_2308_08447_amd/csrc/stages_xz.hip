@@ -566,11 +566,11 @@ static int launch_xz(XZBatch b, int nx, int nz, int variant, const float2* tw, h
     bool done = false;
 #define XZ_LAUNCH(V)                                                                               \
     if (INVERSE)                                                                                   \
-        DM_LAUNCH((xz_inverse_kernel<L, NZS, V>), dim3(grid), dim3(XZShape<L>::NTA), 0, s, \
-                           b, tw);                                                                 \
+        DM_LAUNCH((xz_inverse_kernel<L, NZS, V>), dim3(grid), dim3(XZShape<L>::NTA), 0, s,         \
+                  b, tw);                                                                          \
     else                                                                                           \
-        DM_LAUNCH((xz_forward_kernel<L, NZS, V>), dim3(grid), dim3(XZShape<L>::NTA), 0, s, \
-                           b, tw);
+        DM_LAUNCH((xz_forward_kernel<L, NZS, V>), dim3(grid), dim3(XZShape<L>::NTA), 0, s,         \
+                  b, tw);
 #define NZS_CASE(NZv)                       \
     if (nz == NZv) {                        \
         constexpr int NZS = NZv;            \
@@ -620,16 +620,16 @@ int launch_yconv(YCBatch b, int ny, int Nz, int variant, const float2* tw, hipSt
     if (Nz == NZv) {                                                                                  \
         if constexpr (LNY >= 2 * NT) {                                                                \
             if (LNY <= 1024 && variant == 0)                                                          \
-                DM_LAUNCH((yconv_reg_kernel<LNY, NZv, (LNY <= 1024 ? 128 : 256), false>),    \
-                                   dim3(grid), dim3(LNY <= 1024 ? 128 : 256), 0, s, b, tw);           \
+                DM_LAUNCH((yconv_reg_kernel<LNY, NZv, (LNY <= 1024 ? 128 : 256), false>),             \
+                          dim3(grid), dim3(LNY <= 1024 ? 128 : 256), 0, s, b, tw);                    \
             else if (variant == 2)                                                                    \
-                DM_LAUNCH((yconv_reg_kernel<LNY, NZv, 256, true>), dim3(grid), dim3(256), 0, \
-                                   s, b, tw);                                                         \
+                DM_LAUNCH((yconv_reg_kernel<LNY, NZv, 256, true>), dim3(grid), dim3(256), 0,          \
+                          s, b, tw);                                                                  \
             else                                                                                      \
-                DM_LAUNCH((yconv_reg_kernel<LNY, NZv, 256, false>), dim3(grid), dim3(256), 0, \
-                                   s, b, tw);                                                         \
+                DM_LAUNCH((yconv_reg_kernel<LNY, NZv, 256, false>), dim3(grid), dim3(256), 0,         \
+                          s, b, tw);                                                                  \
         } else {                                                                                      \
-            DM_LAUNCH((yconv_kernel<LNY, NZv>), dim3(grid), dim3(NT), 0, s, b, tw);          \
+            DM_LAUNCH((yconv_kernel<LNY, NZv>), dim3(grid), dim3(NT), 0, s, b, tw);                   \
         }                                                                                             \
         done = true;                                                                                  \
     }

@@ -95,11 +95,11 @@ static int launch_y(YBatch b, int ny, int variant, int mf, const float2* tw, hip
         for (int r = 0; r < b.count; ++r)                                                     \
             b.start[r + 1] = b.start[r] + ((b.d[r].nk + LPB - 1) / LPB) * b.d[r].nz * 3;     \
         if (INVERSE)                                                                          \
-            DM_LAUNCH((y_inverse_kernel<L, LPB, 0, true>),                           \
-                               dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);       \
+            DM_LAUNCH((y_inverse_kernel<L, LPB, 0, true>),                                    \
+                      dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);                \
         else                                                                                  \
-            DM_LAUNCH((y_forward_kernel<L, LPB, 0, true>),                           \
-                               dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);       \
+            DM_LAUNCH((y_forward_kernel<L, LPB, 0, true>),                                    \
+                      dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);                \
         break;                                                                                \
     }
             DM_POW2_CASES(CASE)
@@ -120,11 +120,11 @@ static int launch_y(YBatch b, int ny, int variant, int mf, const float2* tw, hip
         for (int r = 0; r < b.count; ++r)                                                     \
             b.start[r + 1] = b.start[r] + ((b.d[r].nk + LPB - 1) / LPB) * b.d[r].nz * 3;     \
         if (INVERSE)                                                                          \
-            DM_LAUNCH((y_inverse_kernel<L, LPB, 0, false>),                          \
-                               dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);       \
+            DM_LAUNCH((y_inverse_kernel<L, LPB, 0, false>),                                   \
+                      dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);                \
         else                                                                                  \
-            DM_LAUNCH((y_forward_kernel<L, LPB, 0, false>),                          \
-                               dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);       \
+            DM_LAUNCH((y_forward_kernel<L, LPB, 0, false>),                                   \
+                      dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);                \
         break;                                                                                \
     }
             DM_MIXED_CASES(CASE)
@@ -142,11 +142,11 @@ static int launch_y(YBatch b, int ny, int variant, int mf, const float2* tw, hip
         for (int r = 0; r < b.count; ++r)                                                       \
             b.start[r + 1] = b.start[r] + ((b.d[r].nk + LPB - 1) / LPB) * b.d[r].nz * 3;       \
         if (INVERSE)                                                                            \
-            DM_MF_DISPATCH(V, DM_LAUNCH((y_inverse_kernel<L, LPB, MFv>),               \
-                               dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)        \
+            DM_MF_DISPATCH(V, DM_LAUNCH((y_inverse_kernel<L, LPB, MFv>),                        \
+                      dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)                 \
         else                                                                                    \
-            DM_MF_DISPATCH(V, DM_LAUNCH((y_forward_kernel<L, LPB, MFv>),               \
-                               dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)        \
+            DM_MF_DISPATCH(V, DM_LAUNCH((y_forward_kernel<L, LPB, MFv>),                        \
+                      dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)                 \
     }
 #define CASE(Lv)                    \
     case Lv: {                      \

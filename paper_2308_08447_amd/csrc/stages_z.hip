@@ -447,8 +447,8 @@ int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, h
             int th = TH < ny ? TH : ny;                                                        \
             b.start[r + 1] = b.start[r] + ((ny + th - 1) / th) * b.d[r].nk;                   \
         }                                                                                      \
-        DM_LAUNCH((z_convolve_kernel<NZ, TH, 0, true>), dim3((unsigned)finish_batch(b)), \
-                           dim3(NT), 0, s, b, tw);                                             \
+        DM_LAUNCH((z_convolve_kernel<NZ, TH, 0, true>), dim3((unsigned)finish_batch(b)),       \
+                  dim3(NT), 0, s, b, tw);                                                      \
         break;                                                                                 \
     }
             CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64) CASE(128)
@@ -486,20 +486,20 @@ int launch_z_convolve(ZBatch b, int Nz, int variant, int mf, const float2* tw, h
             if (sq) {                                                                          \
                 for (int r = 0; r < b.count; ++r)                                              \
                     b.start[r + 1] = b.start[r] + (b.d[r].Ny / CBQ) * b.d[r].nk;               \
-                DM_LAUNCH((z_convolve_sq_kernel<NZ, CBQ>), dim3((unsigned)finish_batch(b)), \
-                                   dim3(CBQ * 8), 0, s, b, tw);                                \
+                DM_LAUNCH((z_convolve_sq_kernel<NZ, CBQ>), dim3((unsigned)finish_batch(b)),    \
+                          dim3(CBQ * 8), 0, s, b, tw);                                         \
                 break;                                                                         \
             }                                                                                  \
         }                                                                                      \
         if constexpr (NZ >= 2) {                                                               \
             if (lean) {                                                                        \
-                DM_LAUNCH((z_convolve_lean_kernel<NZ, THL, CPB>),                    \
-                                   dim3((unsigned)finish_batch(b)), dim3(NTZ), 0, s, b, tw);  \
+                DM_LAUNCH((z_convolve_lean_kernel<NZ, THL, CPB>),                              \
+                          dim3((unsigned)finish_batch(b)), dim3(NTZ), 0, s, b, tw);            \
                 break;                                                                         \
             }                                                                                  \
         }                                                                                      \
-        DM_MF_DISPATCH(V, DM_LAUNCH((z_convolve_kernel<NZ, TH, MFv>),                \
-                           dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)          \
+        DM_MF_DISPATCH(V, DM_LAUNCH((z_convolve_kernel<NZ, TH, MFv>),                          \
+                  dim3((unsigned)finish_batch(b)), dim3(NT), 0, s, b, tw);)                    \
     }
 #define CASE(NZv)                   \
     case NZv: {                     \
