@@ -293,6 +293,58 @@ def test_abi_rejects_bad_arguments(gpu_lib, torch_dev):
         pkg.demag_destroy(plan)
 
 
+@pytest.mark.parametrize("n,nch", [((128, 64, 8), 1), ((64, 32, 32), 3)], ids=["thin", "five-pass"])
+def test_stage_timing_counts_and_bounds(gpu_lib, torch_dev, n, nch):
+    """Per-stage timing: each timed launch takes its record's two events, so
+    every stage launch is counted once, each recorded time is positive, the
+    recorded kernel times of K evaluations add up to no more than their wall
+    time, and the field is the same bits as untimed.  RK4 steps record four
+    LLG stage launches each."""
+    import paper_2308_08447_amd as pkg
+    torch = torch_dev
+    _say("stage timing", n, nch)
+    plan = pkg.demag_setup(n + W.CELL_4NM)
+    try:
+        thin = pkg.demag_get_form(plan) == pkg.DEMAG_FORM_THIN
+        if not thin:
+            pkg.demag_set_chunks(plan, nch)
+        nch = pkg.demag_get_chunks(plan)
+        M = torch.from_numpy(W.magnetisation(n, 3)).cuda()
+        ref = torch.empty_like(M)
+        pkg.demag_field(plan, M, ref)
+        K = 3
+        pkg.demag_timing_enable(plan, K * nch)
+        H = torch.empty_like(M)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(K):
+            pkg.demag_field(plan, M, H)
+        e1.record()
+        torch.cuda.synchronize()
+        rec = pkg.demag_timing_read(plan)
+        wall_ms = e0.elapsed_time(e1)
+        want = {"x_fwd": K, "z_conv": K, "x_inv": K} if thin else \
+            {"x_fwd": K, "y_fwd": K * nch, "z_conv": K * nch, "y_inv": K * nch, "x_inv": K}
+        _say("  records", rec, "wall ms", wall_ms)
+        for st, cnt in want.items():
+            assert rec[st][1] == cnt, (st, rec[st])
+            assert rec[st][0] > 0.0, (st, rec[st])
+        assert rec["llg"][1] == 0
+        assert sum(rec[st][0] for st in want) <= wall_ms
+        assert torch.equal(H, ref)
+        m = torch.from_numpy(W.unit_vectors((n[2], n[1], n[0]), seed=4)).cuda()
+        pkg.demag_timing_enable(plan, 4 * 2 * nch)
+        pkg.llg_step(plan, m, (W.MS, W.A_EX, 0.1, ollg.GAMMA, (0, 0, 0)), 1e-13, 2)
+        torch.cuda.synchronize()
+        rec = pkg.demag_timing_read(plan)
+        assert rec["llg"][1] == 8 and rec["llg"][0] > 0.0
+        assert rec["x_fwd"][1] == 8
+        pkg.demag_timing_enable(plan, 0)
+    finally:
+        pkg.demag_destroy(plan)
+
+
 # ------------------------------------------------------------------ LLG (RK4)
 @pytest.mark.parametrize("n,steps", [((16, 8, 2), 1), ((16, 8, 2), 10), ((32, 32, 4), 10),
                                      ((1, 1, 1), 20), ((64, 1, 1), 5)])
